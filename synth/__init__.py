@@ -1,0 +1,110 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
+
+This module holds none of the method's arithmetic: it only draws random
+numbers and lays out arrays.  It stands in for the paper's simulated Cyg A
+cube and VLA data (Sec. 4.1), which are not available here.
+
+Cube recipe (per-blob simplification of the power-law spectral model of
+Sec. 4.1): X[n, l] = sum_b A_b exp(-|r_n - c_b|^2 / (2 s_b^2)) (nu_l / nu_1)^{alpha_b}
+with centres c_b uniform over the image, widths s_b ~ U(1, 8) px, spectral
+indices alpha_b ~ U(-1, 1), amplitudes log-uniform on [1e-3, 1]; every blob is
+evaluated within 6 s_b of its centre.  Frequencies are uniform over
+[2.052, 3.572] GHz (L <= 64) or [2.052, 3.636] GHz (L = 100), the bands of the
+two experiments of Sec. 4.1.  The cube is drawn in float64 and rounded once to
+float32; every consumer uses the rounded values.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    ny: int
+    nx: int
+    L: int
+    qy: int
+    qx: int
+    overlap: int       # low-rankness overlap in pixels, toward top/left
+    C: int = 1         # spectral sub-cubes (channel-interleaved)
+    blobs: int = 50
+    levels: int = 4
+    seed_offset: int = 0
+
+    @property
+    def voxels(self):
+        return self.ny * self.nx * self.L
+
+
+WORKLOADS = {
+    "cfg1_256x256x20": Workload("cfg1_256x256x20", 256, 256, 20, 2, 2, 32, 1, 50, 4, 1),
+    "cfg2_1024x2048x20": Workload("cfg2_1024x2048x20", 1024, 2048, 20, 4, 4, 64, 1, 50, 4, 2),
+    "cfg3_2048x2048x60": Workload("cfg3_2048x2048x60", 2048, 2048, 60, 8, 8, 26, 1, 3200, 4, 3),
+    "cfg4_2048x2048x100_c10": Workload("cfg4_2048x2048x100_c10", 2048, 2048, 100, 8, 8, 26, 10, 3200, 4, 4),
+    "cfg5_4096x4096x64": Workload("cfg5_4096x4096x64", 4096, 4096, 64, 16, 16, 128, 1, 12800, 4, 5),
+}
+
+BASE_SEED = 200307358
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def frequencies(L):
+    hi = 3.636 if L == 100 else 3.572
+    return np.linspace(2.052, hi, L)
+
+
+def blob_cube(ny, nx, L, nblobs, seed):
+    """float32 (ny, nx, L) sum of Gaussian blobs with power-law spectra."""
+    g = rng(seed)
+    cy = g.uniform(0, ny, nblobs)
+    cx = g.uniform(0, nx, nblobs)
+    s = g.uniform(1.0, 8.0, nblobs)
+    alpha = g.uniform(-1.0, 1.0, nblobs)
+    amp = 10.0 ** g.uniform(-3.0, 0.0, nblobs)
+    nu = frequencies(L)
+    X = np.zeros((ny, nx, L), dtype=np.float64)
+    for b in range(nblobs):
+        r = int(np.ceil(6 * s[b]))
+        y0, y1 = max(0, int(cy[b]) - r), min(ny, int(cy[b]) + r + 1)
+        x0, x1 = max(0, int(cx[b]) - r), min(nx, int(cx[b]) + r + 1)
+        if y0 >= y1 or x0 >= x1:
+            continue
+        gy = np.exp(-((np.arange(y0, y1) - cy[b]) ** 2) / (2 * s[b] ** 2))
+        gx = np.exp(-((np.arange(x0, x1) - cx[b]) ** 2) / (2 * s[b] ** 2))
+        spec = amp[b] * (nu / nu[0]) ** alpha[b]
+        X[y0:y1, x0:x1] += (gy[:, None] * gx[None, :])[..., None] * spec[None, None, :]
+    return X.astype(np.float32)
+
+
+def uniform_weights(n, seed, lo=0.5, hi=1.0):
+    return rng(seed).uniform(lo, hi, n).astype(np.float32)
+
+
+def sorted_weights(n, seed, lo=0.5, hi=1.0):
+    """Ascending U(lo, hi) weights (float64), one draw per facet."""
+    return np.sort(rng(seed).uniform(lo, hi, n))
+
+
+def gaussian(shape, seed, scale):
+    return (scale * rng(seed).standard_normal(shape)).astype(np.float32)
+
+
+def sigma_bar(X):
+    """Noise-level stand-in: 1e-3 max(X) (the paper's estimate needs the
+    measurement operator, which is out of scope)."""
+    return 1e-3 * float(np.max(X))
+
+
+def workload_cube(w: Workload, variant="plain"):
+    """X_check for a workload.  'plain': X; 'signed': 2 X_a - X_b with X_b from
+    the next seed (the extrapolated iterate of Algorithm 2 can be negative)."""
+    seed = BASE_SEED + w.seed_offset
+    Xa = blob_cube(w.ny, w.nx, w.L, w.blobs, seed)
+    if variant == "plain":
+        return Xa
+    Xb = blob_cube(w.ny, w.nx, w.L, w.blobs, seed + 1000)
+    return (2.0 * Xa.astype(np.float64) - Xb).astype(np.float32)
