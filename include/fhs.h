@@ -1,0 +1,214 @@
+/*
+ * fhs.h -- C ABI of the facet-wise regularization step of Faceted HyperSARA
+ * (Thouvenin, Abdulaziz, Dabbech, Repetti, Wiaux, arXiv:2003.07358) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Scope.  One PDFB iteration of Algorithm 2 updates, for every spectral
+ * sub-cube c and spatial facet q, two dual variables and aggregates their
+ * contributions into the primal gradient:
+ *
+ *   nuclear  (Alg. 2, step alg:step:dual_lr; Table 1 SVT):
+ *     P_{c,q} <- (I - prox_{zeta^-1 mu_bar_{c,q} ||.||_{*,theta_bar_{c,q}}})(P_{c,q} + D_q S~_q Xcheck_c)
+ *   l21      (Alg. 2, step alg:step:dual_sparsity; Table 1 row shrink):
+ *     W_{c,q} <- (I - prox_{kappa^-1 mu_c ||.||_{2,1,theta_{c,q}}})(W_{c,q} + Psi_q^dagger S_q Xcheck_c)
+ *   gather   (Alg. 2, step alg:step:aggregate, facet part):
+ *     G_c = sum_q zeta S~_q^T D_q P_{c,q} + kappa S_q^T Psi_q W_{c,q}
+ *
+ * Psi^dagger is the SARA dictionary (Sec. 2.3.1): Daubechies db1..db8 at
+ * `levels` levels plus the Dirac basis, divided by 3.  The faceted transform is
+ * exactly the global one (Sec. 2.4.2), so W is held in the global coefficient
+ * layout and every facet owns a rectangle of each band.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Arrays.   Every array argument of a compute call is a DEVICE pointer owned by
+ *           the caller (e.g. a torch tensor).  The library never frees, never
+ *           allocates device memory in a compute call and never synchronises
+ *           the host; every compute call is asynchronous on `stream`
+ *           (a hipStream_t passed as void*, NULL = the null stream).
+ * Cube.     X, Xcheck, G: float32 [ny][nx][L], channels contiguous (pixels are
+ *           rows and channels columns of the N x L matrix of Sec. 2.2).
+ * Sub-cubes. Channel-interleaved (Sec. 2.4.1): sub-cube c holds the channels
+ *           c, c + C, c + 2C, ...; C must divide L, L_c = L / C <= 64.
+ *           Channel "position" p = c * L_c + l stands for channel c + l * C.
+ * P.        float32, packed per facet f = c * Q + q in that order, each facet a
+ *           row-major [ny~_q][nx~_q][L_c] block (offsets from fhs_plan_facet).
+ * W.        float32 [I][L]: coefficient row i (a position in a band), then the
+ *           L channel positions p (sub-cube-major).  Band order: db1 .. db8,
+ *           each as (lh, hl, hh) for level 1 .. levels, then ll of the last
+ *           level; finally the Dirac band [ny][nx].  I = fhs_sizes.n_coef.
+ * theta.    float32 [C][I]: one l21 weight per coefficient row and sub-cube.
+ * theta_bar float64 [C*Q][L_c]: nuclear weights of facet f, paired with the
+ *           singular values in descending order.
+ * mu        float64 [C]      (mu_c of eq. heuristic_fhs_sparsity).
+ * mu_bar    float64 [C*Q]    (mu_bar_{c,q} of eq. heuristic_fhs_low_rank).
+ * Workspace. Caller-owned device memory of fhs_sizes.workspace_bytes bytes,
+ *           attached once with fhs_plan_set_workspace; compute calls use it as
+ *           scratch, so calls that share a plan must not overlap in time.
+ * Errors.   Every int-returning function returns FHS_OK (0) or a negative
+ *           code; fhs_last_error() returns a thread-local message.  No C++
+ *           exception crosses the ABI.  A HIP launch error is reported as
+ *           FHS_EHIP; execution errors surface on the stream, as usual.
+ */
+#ifndef FHS_H
+#define FHS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FHS_OK 0
+#define FHS_EINVAL (-1)         /* bad argument (null pointer, size, range) */
+#define FHS_EHIP (-2)           /* a HIP runtime call failed */
+#define FHS_ENOMEM (-3)         /* host allocation failed */
+#define FHS_EUNSUPPORTED (-4)   /* valid but unsupported configuration */
+#define FHS_ENOWORKSPACE (-5)   /* compute call before fhs_plan_set_workspace */
+
+typedef struct fhs_plan fhs_plan;   /* opaque; immutable geometry after creation */
+
+typedef struct {
+  int32_t ny, nx;        /* image size, N = ny * nx                                  */
+  int32_t nchan;         /* L, channels of the cube                                  */
+  int32_t qy, qx;        /* spatial facet grid, Q = qy * qx (Sec. 2.4.2)            */
+  int32_t n_sub;         /* C, interleaved spectral sub-cubes (Sec. 2.4.1); 1 = none */
+  int32_t overlap_y;     /* low-rankness overlap in pixels toward the top (Sec. 2.4.2) */
+  int32_t overlap_x;     /* ... toward the left                                      */
+  int32_t levels;        /* wavelet decomposition levels (1..6; 4 in the paper)      */
+} fhs_config;
+
+typedef struct {
+  int64_t n_x;              /* floats of X, Xcheck, G: ny*nx*L                 */
+  int64_t n_p;              /* floats of the packed P                          */
+  int64_t n_coef;           /* I, coefficient rows of Psi^dagger               */
+  int64_t n_w;              /* floats of W: I * L                              */
+  int64_t n_theta;          /* floats of theta: C * I                          */
+  int64_t n_facets;         /* C * Q                                           */
+  int64_t n_theta_bar;      /* doubles of theta_bar: C * Q * L_c               */
+  int64_t n_bands;          /* bands of Psi^dagger: 8 * (3 levels + 1) + 1     */
+  int64_t workspace_bytes;  /* bytes for fhs_plan_set_workspace                */
+} fhs_sizes;
+
+/* ---------------------------------------------------------------- host only */
+
+/* Library version (major * 100 + minor). */
+int fhs_version(void);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *fhs_last_error(void);
+
+/* Daubechies extremal-phase scaling filter dbN, N = 1..8 (the eight wavelet
+ * bases of the SARA dictionary, Sec. 2.3.1), derived by the library by
+ * spectral factorisation of the Daubechies polynomial.  Writes 2N doubles to
+ * the HOST array h_out.  High-pass: g[m] = (-1)^m h[2N-1-m]. */
+int fhs_filter(int32_t N, double *h_out);
+
+/* Mean and standard deviation of a chi distribution with k degrees of
+ * freedom (used by eqs. heuristic_hypersara_sparsity and heuristic_fhs_sparsity).
+ * HOST pointers. */
+int fhs_chi_mean_std(double k, double *mean, double *std_dev);
+
+/* Builds the geometry: tiles t_s = floor(s n / Q); low-rankness facets
+ * extended by the overlap toward top/left, edge facets keeping the tile size
+ * (Sec. 2.4.2); band sizes of the zero-extended expansive transform; packed
+ * offsets; workspace size.  Host memory only.  *out receives the plan. */
+int fhs_plan_create(const fhs_config *cfg, fhs_plan **out);
+void fhs_plan_destroy(fhs_plan *plan);
+int fhs_plan_sizes(const fhs_plan *plan, fhs_sizes *out);
+
+/* Facet f (0 <= f < C*Q) as 12 int64 on the HOST:
+ * {c, sy, sx, tile_y0, tile_y1, tile_x0, tile_x1,
+ *  win_y0, win_y1, win_x0, win_x1, p_offset (floats into the packed P)}. */
+int fhs_plan_facet(const fhs_plan *plan, int32_t f, int64_t out[12]);
+
+/* Band k (storage order) as 4 int64 on the HOST: {rows, cols, first
+ * coefficient row, level (0 for the Dirac band)}. */
+int fhs_plan_band(const fhs_plan *plan, int32_t k, int64_t out[4]);
+
+/* Regularisation parameters from the noise level sigma_bar_c (HOST arrays):
+ * mu_c = sigma_bar_c (m_chi(L_c) + s_chi(L_c))            (eq. heuristic_fhs_sparsity)
+ * mu_bar_{c,q} = sigma_bar_c sqrt(N~_q L_c / min(N~_q, L_c)) (eq. heuristic_fhs_low_rank)
+ * sigma_bar [C] in, mu [C] out, mu_bar [C*Q] out. */
+int fhs_plan_heuristics(const fhs_plan *plan, const double *sigma_bar, double *mu, double *mu_bar);
+
+/* Attaches caller-owned device scratch of at least fhs_sizes.workspace_bytes
+ * bytes (256-byte aligned).  The plan keeps the pointer, not the memory. */
+int fhs_plan_set_workspace(fhs_plan *plan, void *dev_ptr, int64_t bytes);
+
+/* ---------------------------------------------------------------- compute */
+
+/* w = Psi^dagger x (Sec. 2.3.1): all nine bases, divided by 3; x [ny][nx][L]
+ * in natural channel order, w [I][L] in channel positions. */
+int fhs_sara_analysis(const fhs_plan *plan, const float *x, float *w, void *stream);
+
+/* x = beta x + alpha Psi w, Psi the adjoint of Psi^dagger (Alg. 2, step
+ * alg:step:end_facet-l21 summed over facets). */
+int fhs_sara_synthesis(const fhs_plan *plan, const float *w, float *x, float alpha, float beta,
+                       void *stream);
+
+/* l21 dual update of every facet (Alg. 2, step alg:step:dual_sparsity) and its
+ * gather: for every coefficient row i and sub-cube c,
+ *   u = W_i + [Psi^dagger Xcheck_c]_i,  W_i <- u min(1, (mu_c / kappa) theta_{c,i} / ||u||_2)
+ *   (W_i <- 0 when u = 0),
+ * then grad = beta grad + kappa Psi W.  W is updated in place; grad must not
+ * alias xcheck or w_inout. */
+int fhs_l21_dual_update(const fhs_plan *plan, const float *xcheck, float *w_inout,
+                        const float *theta, const double *mu, double kappa, float *grad,
+                        float beta, void *stream);
+
+/* Weighted nuclear-norm dual update of every facet (Alg. 2, step
+ * alg:step:dual_lr) and its gather: Z = P_f + D_q S~_q Xcheck_c (N~_q x L_c),
+ * thresholds t_j = (mu_bar_f / zeta) theta_bar_{f,j} paired with the singular
+ * values s_1 >= s_2 >= ..., and
+ *   P_f <- Z - prox(Z) = U Diag(min(s_j, t_j)) V^T = Z V Diag(min(1, t_j / s_j)) V^T,
+ * then grad = beta grad + zeta sum_f S~_q^T D_q P_f (step
+ * alg:step:end_facet-nuclear and the aggregation).  P is updated in place. */
+int fhs_nuclear_dual_update(const fhs_plan *plan, const float *xcheck, float *p_inout,
+                            const double *theta_bar, const double *mu_bar, double zeta,
+                            float *grad, float beta, void *stream);
+
+/* Both dual updates and the full facet part of the aggregation (Alg. 2,
+ * facet loop and step alg:step:aggregate):
+ *   grad = zeta sum_f S~_q^T D_q P_f + kappa Psi W   (grad overwritten). */
+int fhs_facet_prox_step(const fhs_plan *plan, const float *xcheck, float *p_inout,
+                        float *w_inout, const float *theta, const double *theta_bar,
+                        const double *mu, const double *mu_bar, double zeta, double kappa,
+                        float *grad, void *stream);
+
+/* Reweighting weights from the previous iterate X^(t) (Alg. 1, steps
+ * alg:step:weights_nuclear and alg:step:weights_l21):
+ *   theta_bar_{f,j} = upsilon_bar_f / (s_j(D_q S~_q X_c) + upsilon_bar_f)  (eq. facet_hypersara_rank)
+ *   theta_{c,i}     = upsilon_c / (||[Psi^dagger X_c]_i||_2 + upsilon_c)    (eq. facet_hypersara_sparsity)
+ * upsilon [C] and upsilon_bar [C*Q] are float64 device arrays. */
+int fhs_reweight(const fhs_plan *plan, const float *x, const double *upsilon,
+                 const double *upsilon_bar, float *theta, double *theta_bar, void *stream);
+
+/* ---------------------------------------------------------------- diagnostics */
+
+/* Kernel identifiers for fhs_plan_profile. */
+#define FHS_K_ANALYSIS_L1 0   /* analysis, level 1 of all bases + Dirac (fused l21 update) */
+#define FHS_K_ANALYSIS 1      /* analysis, levels >= 2                                    */
+#define FHS_K_SYNTHESIS 2     /* synthesis, levels >= 2                                   */
+#define FHS_K_SYNTH_FINAL_A 3 /* synthesis level 1, first group of bases + Dirac          */
+#define FHS_K_SYNTH_FINAL_B 4 /* synthesis level 1, second group of bases                 */
+#define FHS_K_NUC_GRAM 5
+#define FHS_K_NUC_EIG 6
+#define FHS_K_NUC_RECON 7
+#define FHS_K_NUC_GATHER 8
+#define FHS_K_COUNT 9
+
+/* Times every launch of kernel `kernel_id` (or none if -1) with HIP events
+ * recorded on the launch stream around it.  Creates up to `max_launches`
+ * event pairs now (host call; not during compute calls).  Returns FHS_OK. */
+int fhs_plan_profile(fhs_plan *plan, int32_t kernel_id, int32_t max_launches);
+
+/* Waits for the recorded events, returns the summed duration (ms) and the
+ * number of timed launches since the last read, and resets the counters. */
+int fhs_plan_profile_read(fhs_plan *plan, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FHS_H */

@@ -1,0 +1,260 @@
+"""ctypes binding of libfhs (include/fhs.h).
+
+Argument marshalling only: sizes, dtypes and contiguity are checked against
+the plan, then raw device pointers and the current HIP stream are passed to the
+C ABI; every step of the computation runs in the library's HIP kernels.  There
+is no fallback: if libfhs.so is missing, using the binding raises FhsError.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfhs.so")
+_lib = None
+
+
+class FhsError(RuntimeError):
+    pass
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("ny", "nx", "nchan", "qy", "qx", "n_sub", "overlap_y", "overlap_x", "levels")]
+
+
+class _Sizes(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("n_x", "n_p", "n_coef", "n_w", "n_theta", "n_facets", "n_theta_bar", "n_bands",
+                 "workspace_bytes")]
+
+
+SYMBOLS = {
+    "fhs_version": (ctypes.c_int, []),
+    "fhs_last_error": (ctypes.c_char_p, []),
+    "fhs_filter": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "fhs_chi_mean_std": (ctypes.c_int, [ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "fhs_plan_create": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_void_p)]),
+    "fhs_plan_destroy": (None, [ctypes.c_void_p]),
+    "fhs_plan_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Sizes)]),
+    "fhs_plan_facet": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "fhs_plan_band": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "fhs_plan_heuristics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "fhs_plan_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "fhs_sara_analysis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_sara_synthesis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float,
+                                          ctypes.c_float, ctypes.c_void_p]),
+    "fhs_l21_dual_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_float,
+                                           ctypes.c_void_p]),
+    "fhs_nuclear_dual_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                               ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
+    "fhs_facet_prox_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_reweight": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "fhs_plan_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_int64)]),
+}
+
+# kernel identifiers of fhs_plan_profile (include/fhs.h)
+KERNELS = {
+    "analysis_l1": 0, "analysis": 1, "synthesis": 2, "synth_final_a": 3, "synth_final_b": 4,
+    "nuc_gram": 5, "nuc_eig": 6, "nuc_recon": 7, "nuc_gather": 8,
+}
+
+
+def lib():
+    """The loaded libfhs (raises FhsError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise FhsError(f"{_LIB_PATH} is missing: build it with `python -m paper_2003_07358_amd.build`")
+        handle = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in SYMBOLS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def _check(rc):
+    if rc != 0:
+        raise FhsError(f"libfhs error {rc}: {lib().fhs_last_error().decode()}")
+
+
+def _dptr(arr):
+    return ctypes.cast(arr.ctypes.data, ctypes.POINTER(ctypes.c_double))
+
+
+def filter_taps(N):
+    """dbN scaling filter as derived by the library (host computation)."""
+    out = np.zeros(2 * N, dtype=np.float64)
+    _check(lib().fhs_filter(N, _dptr(out)))
+    return out
+
+
+def chi_mean_std(k):
+    m, s = ctypes.c_double(), ctypes.c_double()
+    _check(lib().fhs_chi_mean_std(float(k), ctypes.byref(m), ctypes.byref(s)))
+    return m.value, s.value
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+class Plan:
+    """Geometry of one problem (include/fhs.h, fhs_plan_create) plus its workspace."""
+
+    def __init__(self, ny, nx, nchan, qy=1, qx=1, n_sub=1, overlap_y=0, overlap_x=0, levels=4):
+        self._lib = lib()
+        self.cfg = _Config(ny, nx, nchan, qy, qx, n_sub, overlap_y, overlap_x, levels)
+        handle = ctypes.c_void_p()
+        _check(self._lib.fhs_plan_create(ctypes.byref(self.cfg), ctypes.byref(handle)))
+        self._p = handle
+        s = _Sizes()
+        _check(self._lib.fhs_plan_sizes(self._p, ctypes.byref(s)))
+        self.sizes = {n: getattr(s, n) for n, _ in _Sizes._fields_}
+        self.ny, self.nx, self.L, self.C = ny, nx, nchan, n_sub
+        self.Lc = nchan // n_sub
+        self.Q = qy * qx
+        self.levels = levels
+        self.workspace = None
+
+    def __del__(self):
+        p = getattr(self, "_p", None)
+        if p is not None and p.value:
+            self._lib.fhs_plan_destroy(p)
+            self._p = None
+
+    # ------------------------------------------------------------ host queries
+    def facet(self, f):
+        out = (ctypes.c_int64 * 12)()
+        _check(self._lib.fhs_plan_facet(self._p, f, out))
+        keys = ("c", "sy", "sx", "ty0", "ty1", "tx0", "tx1", "wy0", "wy1", "wx0", "wx1", "poff")
+        return dict(zip(keys, list(out)))
+
+    def band(self, k):
+        out = (ctypes.c_int64 * 4)()
+        _check(self._lib.fhs_plan_band(self._p, k, out))
+        return tuple(out)
+
+    def bands(self):
+        return [self.band(k) for k in range(self.sizes["n_bands"])]
+
+    def heuristics(self, sigma_bar):
+        sb = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma_bar, dtype=np.float64), (self.C,)))
+        mu = np.zeros(self.C)
+        mub = np.zeros(self.sizes["n_facets"])
+        _check(self._lib.fhs_plan_heuristics(self._p, _dptr(sb), _dptr(mu), _dptr(mub)))
+        return mu, mub
+
+    # ------------------------------------------------------------ device side
+    def attach_workspace(self, device="cuda"):
+        import torch
+        nbytes = max(256, self.sizes["workspace_bytes"])
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-ws.data_ptr()) % 256
+        self.workspace = ws
+        _check(self._lib.fhs_plan_set_workspace(self._p, ctypes.c_void_p(ws.data_ptr() + off), nbytes))
+        return self
+
+    def _t(self, t, n, dtype, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise FhsError(f"{name}: expected a device tensor")
+        if t.dtype != dtype:
+            raise FhsError(f"{name}: expected {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise FhsError(f"{name}: must be contiguous")
+        if t.numel() != n:
+            raise FhsError(f"{name}: expected {n} elements, got {t.numel()}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _need_ws(self):
+        if self.workspace is None:
+            raise FhsError("attach_workspace() first")
+
+    def sara_analysis(self, x, w):
+        import torch
+        self._need_ws()
+        s = self.sizes
+        _check(self._lib.fhs_sara_analysis(self._p, self._t(x, s["n_x"], torch.float32, "x"),
+                                           self._t(w, s["n_w"], torch.float32, "w"), _stream(x)))
+
+    def sara_synthesis(self, w, x, alpha=1.0, beta=0.0):
+        import torch
+        self._need_ws()
+        s = self.sizes
+        _check(self._lib.fhs_sara_synthesis(self._p, self._t(w, s["n_w"], torch.float32, "w"),
+                                            self._t(x, s["n_x"], torch.float32, "x"), float(alpha),
+                                            float(beta), _stream(x)))
+
+    def l21_dual_update(self, xcheck, w, theta, mu, kappa, grad, beta=0.0):
+        import torch
+        self._need_ws()
+        s = self.sizes
+        _check(self._lib.fhs_l21_dual_update(
+            self._p, self._t(xcheck, s["n_x"], torch.float32, "xcheck"),
+            self._t(w, s["n_w"], torch.float32, "w"), self._t(theta, s["n_theta"], torch.float32, "theta"),
+            self._t(mu, self.C, torch.float64, "mu"), float(kappa),
+            self._t(grad, s["n_x"], torch.float32, "grad"), float(beta), _stream(xcheck)))
+
+    def nuclear_dual_update(self, xcheck, p, theta_bar, mu_bar, zeta, grad, beta=0.0):
+        import torch
+        self._need_ws()
+        s = self.sizes
+        _check(self._lib.fhs_nuclear_dual_update(
+            self._p, self._t(xcheck, s["n_x"], torch.float32, "xcheck"),
+            self._t(p, s["n_p"], torch.float32, "p"),
+            self._t(theta_bar, s["n_theta_bar"], torch.float64, "theta_bar"),
+            self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"), float(zeta),
+            self._t(grad, s["n_x"], torch.float32, "grad"), float(beta), _stream(xcheck)))
+
+    def facet_prox_step(self, xcheck, p, w, theta, theta_bar, mu, mu_bar, zeta, kappa, grad):
+        import torch
+        self._need_ws()
+        s = self.sizes
+        _check(self._lib.fhs_facet_prox_step(
+            self._p, self._t(xcheck, s["n_x"], torch.float32, "xcheck"),
+            self._t(p, s["n_p"], torch.float32, "p"), self._t(w, s["n_w"], torch.float32, "w"),
+            self._t(theta, s["n_theta"], torch.float32, "theta"),
+            self._t(theta_bar, s["n_theta_bar"], torch.float64, "theta_bar"),
+            self._t(mu, self.C, torch.float64, "mu"),
+            self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"), float(zeta), float(kappa),
+            self._t(grad, s["n_x"], torch.float32, "grad"), _stream(xcheck)))
+
+    # ------------------------------------------------------------ diagnostics
+    def profile(self, kernel, max_launches=4096):
+        """Time every launch of `kernel` (name from KERNELS, or None to stop)."""
+        kid = -1 if kernel is None else KERNELS[kernel]
+        _check(self._lib.fhs_plan_profile(self._p, kid, max_launches))
+
+    def profile_read(self):
+        """(total ms, launches) since the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(self._lib.fhs_plan_profile_read(self._p, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def reweight(self, x, upsilon, upsilon_bar, theta, theta_bar):
+        import torch
+        self._need_ws()
+        s = self.sizes
+        _check(self._lib.fhs_reweight(
+            self._p, self._t(x, s["n_x"], torch.float32, "x"),
+            self._t(upsilon, self.C, torch.float64, "upsilon"),
+            self._t(upsilon_bar, s["n_facets"], torch.float64, "upsilon_bar"),
+            self._t(theta, s["n_theta"], torch.float32, "theta"),
+            self._t(theta_bar, s["n_theta_bar"], torch.float64, "theta_bar"), _stream(x)))

@@ -1,0 +1,307 @@
+// Compute entry points of libfhs: argument checks and launch sequences.
+// No device allocation, no host synchronisation: every call only enqueues
+// kernels on the caller's stream, so a sequence of calls can be captured in a
+// HIP graph.
+#include <algorithm>
+#include <cstring>
+
+#include "fhs_internal.h"
+
+using namespace fhs;
+
+namespace {
+
+constexpr int kTkyAna = 64;   // coefficient rows per analysis workgroup
+constexpr int kTySyn = 64;    // output rows per synthesis workgroup (levels >= 2)
+constexpr int kTyFinal = 128; // output rows per final synthesis workgroup
+constexpr int kE = 1;         // coefficient columns per analysis thread
+
+int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+float *ws_f(const fhs_plan *p, int64_t off) { return reinterpret_cast<float *>(static_cast<char *>(p->ws) + off); }
+double *ws_d(const fhs_plan *p, int64_t off) { return reinterpret_cast<double *>(static_cast<char *>(p->ws) + off); }
+
+int thread_cfg(const fhs_plan *p, int *tkx1, int *nthreads) {
+  const int per = p->Lcp * p->C;
+  if (per > 256) return fail(FHS_EUNSUPPORTED, "sub-cubes x padded channels per sub-cube exceed 256");
+  *tkx1 = std::max(1, 256 / per);
+  *nthreads = *tkx1 * per;
+  return FHS_OK;
+}
+
+int check_plan(const fhs_plan *p) {
+  if (!p) return fail(FHS_EINVAL, "null plan");
+  if (!p->ws) return fail(FHS_ENOWORKSPACE, "no workspace attached (fhs_plan_set_workspace)");
+  return FHS_OK;
+}
+
+int64_t coef_off(const fhs_plan *p, int b, int j, int s) {  // s: 0 lh, 1 hl, 2 hh
+  return p->bands[p->band_first[b] + 3 * j + s].off;
+}
+int64_t ll_off(const fhs_plan *p, int b) { return p->bands[p->band_first[b] + 3 * p->cfg.levels].off; }
+int64_t dirac_off(const fhs_plan *p) { return p->bands.back().off; }
+
+// mode 0: w = Psi^dagger x ; mode 1: l21 dual update of w ; mode 2: theta weights
+int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, const double *mu, double inv_kappa,
+                 int mode, void *stream) {
+  int tkx1, nth;
+  if (int rc = thread_cfg(p, &tkx1, &nth)) return rc;
+  const int TKX = kE * tkx1;
+  const int levels = p->cfg.levels;
+  for (int j = 0; j < levels; ++j) {
+    AnaArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.w = w;
+    a.theta = theta;
+    a.mu = mu;
+    a.inv_kappa = inv_kappa;
+    a.I = p->I;
+    a.L = p->L;
+    a.C = p->C;
+    a.Lc = p->Lc;
+    a.Lcp = p->Lcp;
+    a.tkx1 = tkx1;
+    a.tky = kTkyAna;
+    a.mode = mode;
+    int prefix = 0;
+    for (int b = 0; b < kBases; ++b) {
+      AnaBand &B = a.b[b];
+      B.in = j == 0 ? x : ws_f(p, p->ws_ll[b][j - 1]);
+      B.in_natural = j == 0 ? 1 : 0;
+      B.in_ny = p->in_ny[b][j];
+      B.in_nx = p->in_nx[b][j];
+      B.ll_out = j < levels - 1 ? ws_f(p, p->ws_ll[b][j]) : nullptr;
+      B.Ky = p->Ky[b][j];
+      B.Kx = p->Kx[b][j];
+      B.strips = ceil_div(B.Kx, TKX);
+      B.yblocks = ceil_div(B.Ky, kTkyAna);
+      B.ntap = p->ntap[b];
+      for (int s = 0; s < 3; ++s) B.off[s] = coef_off(p, b, j, s);
+      B.off[3] = j == levels - 1 ? ll_off(p, b) : -1;
+      a.wg_prefix[b] = prefix;
+      prefix += B.strips * B.yblocks;
+    }
+    a.wg_prefix[kBases] = prefix;
+    if (j == 0) {
+      AnaBand &D = a.b[kBases];
+      D.in = x;
+      D.in_natural = 1;
+      D.in_ny = p->cfg.ny;
+      D.in_nx = p->cfg.nx;
+      D.off[0] = dirac_off(p);
+      prefix += ceil_div(static_cast<int64_t>(p->cfg.ny) * p->cfg.nx, TKX);
+    }
+    a.wg_prefix[kBases + 1] = prefix;
+    const int lds = (2 * TKX + kMaxTap - 2) * p->L;
+    const int kid = j == 0 ? FHS_K_ANALYSIS_L1 : FHS_K_ANALYSIS;
+    prof_begin(p, kid, stream);
+    const int rc = launch_analysis(a, nth, lds, kE, j == 0, stream);
+    prof_end(p, kid, stream);
+    if (rc) return rc;
+  }
+  return FHS_OK;
+}
+
+// x = beta x + alpha Psi w
+int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, float beta, void *stream) {
+  int tk, nth;
+  if (int rc = thread_cfg(p, &tk, &nth)) return rc;
+  const int L = p->L, levels = p->cfg.levels;
+  for (int j = levels - 1; j >= 1; --j) {  // 0-based level j -> writes low-low band of level j-1
+    SynArgs s;
+    std::memset(&s, 0, sizeof(s));
+    s.L = L;
+    s.Lcp = p->Lcp;
+    s.C = p->C;
+    s.Lc = p->Lc;
+    s.tk = tk;
+    s.ty = kTySyn;
+    int prefix = 0;
+    for (int b = 0; b < kBases; ++b) {
+      SynBand &B = s.b[b];
+      B.ll = j == levels - 1 ? w + ll_off(p, b) * L : ws_f(p, p->ws_ll[b][j]);
+      B.lh = w + coef_off(p, b, j, 0) * L;
+      B.hl = w + coef_off(p, b, j, 1) * L;
+      B.hh = w + coef_off(p, b, j, 2) * L;
+      B.out = ws_f(p, p->ws_ll[b][j - 1]);
+      B.Ky = p->Ky[b][j];
+      B.Kx = p->Kx[b][j];
+      B.ny = p->in_ny[b][j];
+      B.nx = p->in_nx[b][j];
+      B.strips = ceil_div((B.nx + 1) / 2, tk);
+      B.yblocks = ceil_div(B.ny, kTySyn);
+      B.ntap = p->ntap[b];
+      s.wg_prefix[b] = prefix;
+      prefix += B.strips * B.yblocks;
+    }
+    s.wg_prefix[kBases] = prefix;
+    const int lds = 4 * (tk + kMaxTap / 2 - 1) * L;
+    prof_begin(p, FHS_K_SYNTHESIS, stream);
+    const int rc = launch_synthesis(s, nth, lds, stream);
+    prof_end(p, FHS_K_SYNTHESIS, stream);
+    if (rc) return rc;
+  }
+  SynFinalArgs f;
+  std::memset(&f, 0, sizeof(f));
+  for (int b = 0; b < kBases; ++b) {
+    SynBand &B = f.b[b];
+    B.ll = levels == 1 ? w + ll_off(p, b) * L : ws_f(p, p->ws_ll[b][0]);
+    B.lh = w + coef_off(p, b, 0, 0) * L;
+    B.hl = w + coef_off(p, b, 0, 1) * L;
+    B.hh = w + coef_off(p, b, 0, 2) * L;
+    B.Ky = p->Ky[b][0];
+    B.Kx = p->Kx[b][0];
+    B.ny = p->cfg.ny;
+    B.nx = p->cfg.nx;
+    B.ntap = p->ntap[b];
+  }
+  f.dirac = w + dirac_off(p) * L;
+  f.x = x;
+  f.alpha = alpha;
+  f.beta = beta;
+  f.ny = p->cfg.ny;
+  f.nx = p->cfg.nx;
+  f.L = L;
+  f.Lcp = p->Lcp;
+  f.C = p->C;
+  f.Lc = p->Lc;
+  f.tk = tk;
+  f.ty = kTyFinal;
+  f.strips = ceil_div((p->cfg.nx + 1) / 2, tk);
+  f.yblocks = ceil_div(p->cfg.ny, kTyFinal);
+  for (int grp = 0; grp < 2; ++grp) {
+    const int kid = grp == 0 ? FHS_K_SYNTH_FINAL_A : FHS_K_SYNTH_FINAL_B;
+    prof_begin(p, kid, stream);
+    const int rc = launch_synthesis_final(f, nth, grp, stream);
+    prof_end(p, kid, stream);
+    if (rc) return rc;
+  }
+  return FHS_OK;
+}
+
+void fill_geom(const fhs_plan *p, NucGeom &g) {
+  std::memset(&g, 0, sizeof(g));
+  g.ny = p->cfg.ny;
+  g.nx = p->cfg.nx;
+  g.L = p->L;
+  g.C = p->C;
+  g.Lc = p->Lc;
+  g.qy = p->cfg.qy;
+  g.qx = p->cfg.qx;
+  g.oy = p->cfg.overlap_y;
+  g.ox = p->cfg.overlap_x;
+  for (int s = 0; s <= g.qy; ++s) g.ty[s] = p->ty[s];
+  for (int s = 0; s <= g.qx; ++s) g.tx[s] = p->tx[s];
+  g.py[0] = 0;
+  for (int s = 0; s < g.qy; ++s) {
+    const int w0 = s > 0 ? p->ty[s] - g.oy : p->ty[s];
+    g.py[s + 1] = g.py[s] + (p->ty[s + 1] - w0);
+  }
+  g.px[0] = 0;
+  for (int s = 0; s < g.qx; ++s) {
+    const int w0 = s > 0 ? p->tx[s] - g.ox : p->tx[s];
+    g.px[s + 1] = g.px[s] + (p->tx[s + 1] - w0);
+  }
+  g.p_sub = p->p_sub;
+}
+
+// mode 0: dual update of p (+ gather); mode 1: weights only
+int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *theta_bar, const double *mu_bar,
+                double zeta, double *theta_bar_out, float *grad, float beta, int mode, void *stream) {
+  NucArgs a;
+  std::memset(&a, 0, sizeof(a));
+  fill_geom(p, a.g);
+  a.x = x;
+  a.p = pdual;
+  a.gram = ws_d(p, p->ws_gram);
+  a.kmat = ws_d(p, p->ws_kmat);
+  a.sig = ws_d(p, p->ws_sig);
+  a.theta_bar = theta_bar;
+  a.mu_bar = mu_bar;
+  a.theta_bar_out = theta_bar_out;
+  a.inv_zeta = 1.0 / zeta;
+  a.chunks = p->gram_chunks;
+  a.chunk_rows = p->gram_chunk_rows;
+  a.lc16 = p->lc16;
+  a.mode = mode;
+  const int nf = static_cast<int>(p->facets.size());
+  int rc;
+  prof_begin(p, FHS_K_NUC_GRAM, stream);
+  rc = launch_nuc_gram(a, nf, stream);
+  prof_end(p, FHS_K_NUC_GRAM, stream);
+  if (rc) return rc;
+  prof_begin(p, FHS_K_NUC_EIG, stream);
+  rc = launch_nuc_eig(a, nf, stream);
+  prof_end(p, FHS_K_NUC_EIG, stream);
+  if (rc) return rc;
+  if (mode == 1) return FHS_OK;
+  prof_begin(p, FHS_K_NUC_RECON, stream);
+  rc = launch_nuc_recon(a, nf, ceil_div(p->max_rows, 64), stream);
+  prof_end(p, FHS_K_NUC_RECON, stream);
+  if (rc) return rc;
+  GatherArgs ga;
+  std::memset(&ga, 0, sizeof(ga));
+  ga.g = a.g;
+  ga.p = pdual;
+  ga.grad = grad;
+  ga.zeta = zeta;
+  ga.beta = beta;
+  prof_begin(p, FHS_K_NUC_GATHER, stream);
+  rc = launch_nuc_gather(ga, stream);
+  prof_end(p, FHS_K_NUC_GATHER, stream);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fhs_sara_analysis(const fhs_plan *p, const float *x, float *w, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!x || !w) return fail(FHS_EINVAL, "fhs_sara_analysis: null array");
+  return run_analysis(p, x, w, nullptr, nullptr, 1.0, 0, stream);
+}
+
+int fhs_sara_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, float beta, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!x || !w) return fail(FHS_EINVAL, "fhs_sara_synthesis: null array");
+  return run_synthesis(p, w, x, alpha, beta, stream);
+}
+
+int fhs_l21_dual_update(const fhs_plan *p, const float *xcheck, float *w, const float *theta, const double *mu,
+                        double kappa, float *grad, float beta, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!xcheck || !w || !theta || !mu || !grad) return fail(FHS_EINVAL, "fhs_l21_dual_update: null array");
+  if (!(kappa > 0)) return fail(FHS_EINVAL, "kappa must be positive");
+  if (int rc = run_analysis(p, xcheck, w, const_cast<float *>(theta), mu, 1.0 / kappa, 1, stream)) return rc;
+  return run_synthesis(p, w, grad, static_cast<float>(kappa), beta, stream);
+}
+
+int fhs_nuclear_dual_update(const fhs_plan *p, const float *xcheck, float *pdual, const double *theta_bar,
+                            const double *mu_bar, double zeta, float *grad, float beta, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!xcheck || !pdual || !theta_bar || !mu_bar || !grad) return fail(FHS_EINVAL, "fhs_nuclear_dual_update: null array");
+  if (!(zeta > 0)) return fail(FHS_EINVAL, "zeta must be positive");
+  return run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, beta, 0, stream);
+}
+
+int fhs_facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, float *w, const float *theta,
+                        const double *theta_bar, const double *mu, const double *mu_bar, double zeta, double kappa,
+                        float *grad, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!xcheck || !pdual || !w || !theta || !theta_bar || !mu || !mu_bar || !grad)
+    return fail(FHS_EINVAL, "fhs_facet_prox_step: null array");
+  if (!(zeta > 0) || !(kappa > 0)) return fail(FHS_EINVAL, "zeta and kappa must be positive");
+  if (int rc = fhs_l21_dual_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream)) return rc;
+  return run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, stream);
+}
+
+int fhs_reweight(const fhs_plan *p, const float *x, const double *upsilon, const double *upsilon_bar, float *theta,
+                 double *theta_bar, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!x || !upsilon || !upsilon_bar || !theta || !theta_bar) return fail(FHS_EINVAL, "fhs_reweight: null array");
+  if (int rc = run_nuclear(p, x, nullptr, nullptr, upsilon_bar, 1.0, theta_bar, nullptr, 0.0f, 1, stream)) return rc;
+  return run_analysis(p, x, nullptr, theta, upsilon, 1.0, 2, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Internal declarations of libfhs: plan layout and kernel argument blocks.
+// Not part of the ABI (see include/fhs.h).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fhs.h"
+
+namespace fhs {
+
+constexpr int kBases = 8;          // db1 .. db8 (the Dirac basis is handled apart)
+constexpr int kMaxTap = 16;        // db8 has 16 taps
+constexpr int kMaxLevels = 6;
+constexpr int kMaxFacetAxis = 64;  // facets per axis
+constexpr int kMaxLc = 64;         // channels per sub-cube
+
+// ---------------------------------------------------------------- error state
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+// ---------------------------------------------------------------- host math
+// Daubechies scaling filter dbN (2N taps, long double), spectral factorisation.
+std::vector<long double> daubechies(int N);
+void chi_mean_std(double k, double *m, double *s);
+
+// ---------------------------------------------------------------- kernel args
+// One wavelet basis at one level of the analysis.
+struct AnaBand {
+  const float *in;     // input band [in_ny][in_nx][L]
+  float *ll_out;       // low-low output [Ky][Kx][L] (workspace) or null on the last level
+  int in_ny, in_nx;
+  int in_natural;      // 1: input is the cube (natural channel order), 0: positions
+  int Ky, Kx;
+  int strips, yblocks;
+  int ntap;
+  int64_t off[4];      // first coefficient row of lh, hl, hh, ll (ll: last level, else -1)
+};
+
+struct AnaArgs {
+  AnaBand b[kBases + 1];      // [8] = Dirac (elementwise)
+  int wg_prefix[kBases + 2];  // cumulative workgroups per basis
+  float *w;
+  float *theta;               // read (mode 1) or written (mode 2)
+  const double *mu;           // [C] thresholds mu_c (mode 1) or upsilon_c (mode 2)
+  double inv_kappa;
+  int64_t I;
+  int L, C, Lc, Lcp, tkx1, tky;
+  int mode;                   // 0: write Psi^dagger x; 1: l21 dual update; 2: l21 weights
+};
+
+// One wavelet basis at one level of the synthesis (levels >= 2): writes the
+// low-low band of the level above into the workspace.
+struct SynBand {
+  const float *ll;            // [Ky][Kx][L]
+  const float *lh, *hl, *hh;  // [Ky][Kx][L]
+  float *out;                 // [ny][nx][L]
+  int Ky, Kx, ny, nx;
+  int strips, yblocks;
+  int ntap;
+};
+
+struct SynArgs {
+  SynBand b[kBases];
+  int wg_prefix[kBases + 1];
+  int L, Lcp, C, Lc, tk, ty;  // tk: coefficient columns per workgroup (2 tk outputs)
+};
+
+// Level 1 of the synthesis for all bases at once, plus the Dirac basis,
+// accumulated into the image: x = beta x + alpha / 3 (sum_b ... + w_dirac).
+struct SynFinalArgs {
+  SynBand b[kBases];          // out, strips, yblocks unused per basis
+  const float *dirac;         // [ny][nx][L] (positions)
+  float *x;                   // [ny][nx][L] natural channel order
+  float alpha, beta;
+  int ny, nx, L, Lcp, C, Lc, tk, ty, strips, yblocks;
+};
+
+// Facet geometry for the nuclear kernels (Sec. 2.4.2).
+struct NucGeom {
+  int ny, nx, L, C, Lc, qy, qx, oy, ox;
+  int ty[kMaxFacetAxis + 1], tx[kMaxFacetAxis + 1];  // tile bounds
+  int py[kMaxFacetAxis + 1], px[kMaxFacetAxis + 1];  // prefix sums of window heights / widths
+  int64_t p_sub;  // floats of P per sub-cube
+};
+
+struct NucArgs {
+  NucGeom g;
+  const float *x;            // cube [ny][nx][L]
+  float *p;                  // packed P
+  double *gram;              // [facets][chunks][Lc16][Lc16] partial Gram matrices
+  double *kmat;              // [facets][Lc16][Lc16] K = V Diag(h) V^T
+  double *sig;               // [facets][Lc] singular values (descending)
+  const double *theta_bar;   // [facets][Lc]
+  const double *mu_bar;      // [facets] (or upsilon_bar for the weights)
+  double *theta_bar_out;     // reweighting output or null
+  double inv_zeta;
+  int chunks;                // row chunks per facet (grid.x of the Gram kernel)
+  int chunk_rows;            // rows per chunk
+  int lc16;                  // Lc rounded up to 16
+  int mode;                  // 0: dual update; 1: weights only
+};
+
+struct GatherArgs {
+  NucGeom g;
+  const float *p;
+  float *grad;
+  double zeta;
+  float beta;
+};
+
+// ---------------------------------------------------------------- launchers
+int launch_analysis(const AnaArgs &a, int nthreads, int lds_floats, int E, bool first, void *stream);
+int launch_synthesis(const SynArgs &a, int nthreads, int lds_floats, void *stream);
+int launch_synthesis_final(const SynFinalArgs &a, int nthreads, int group, void *stream);
+int launch_nuc_gram(const NucArgs &a, int nfacets, void *stream);
+int launch_nuc_eig(const NucArgs &a, int nfacets, void *stream);
+int launch_nuc_recon(const NucArgs &a, int nfacets, int rowblocks, void *stream);
+int launch_nuc_gather(const GatherArgs &a, void *stream);
+
+}  // namespace fhs
+
+// ---------------------------------------------------------------- the plan
+struct fhs_plan {
+  fhs_config cfg{};
+  int L = 0, C = 1, Lc = 0, Q = 0, Lcp = 0, lc16 = 0;
+  std::vector<int> ty, tx;                 // tile bounds
+  struct Facet {
+    int c, sy, sx, ty0, ty1, tx0, tx1, wy0, wy1, wx0, wx1;
+    int64_t poff, rows;
+  };
+  std::vector<Facet> facets;
+  int64_t n_p = 0, p_sub = 0;
+  struct Band { int64_t rows, cols, off; int level; };
+  std::vector<Band> bands;
+  int64_t I = 0;
+  // per basis b, level j (0-based): input dims and band dims
+  int in_ny[fhs::kBases][fhs::kMaxLevels], in_nx[fhs::kBases][fhs::kMaxLevels];
+  int Ky[fhs::kBases][fhs::kMaxLevels], Kx[fhs::kBases][fhs::kMaxLevels];
+  int64_t band_first[fhs::kBases];         // index into `bands` of the basis' first band
+  float h[fhs::kBases][fhs::kMaxTap], g[fhs::kBases][fhs::kMaxTap];
+  int ntap[fhs::kBases];
+  // workspace layout (bytes)
+  int64_t ws_ll[fhs::kBases][fhs::kMaxLevels];
+  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_bytes = 0;
+  int gram_chunks = 0, gram_chunk_rows = 0, max_rows = 0;
+  void *ws = nullptr;
+  int64_t ws_given = 0;
+  // optional per-kernel event timing (diagnostics)
+  mutable int prof_kernel = -1;
+  mutable std::vector<void *> prof_events;  // hipEvent_t pairs
+  mutable int prof_next = 0;
+};
+
+namespace fhs {
+// Records the start / stop events around one launch when profiling `kid`.
+void prof_begin(const fhs_plan *p, int kid, void *stream);
+void prof_end(const fhs_plan *p, int kid, void *stream);
+void prof_release(fhs_plan *p);
+}  // namespace fhs

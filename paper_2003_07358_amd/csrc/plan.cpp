@@ -1,0 +1,257 @@
+// Plan creation and host-only ABI entry points of libfhs.
+//
+// Geometry (Sec. 2.4.2): tiles t_s = floor(s n / Q) per axis; the low-rankness
+// facet of tile s extends `overlap` pixels toward the top/left except on the
+// first row/column of tiles, where it keeps the tile size; the apodisation
+// window D_q is evaluated on the fly by the kernels from these bounds.
+// Wavelet bands: zero-extended expansive transform, K = floor((n + L - 1) / 2)
+// coefficients per band and level for an input of n samples and L taps.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "fhs_internal.h"
+
+namespace fhs {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+static int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+}  // namespace fhs
+
+using namespace fhs;
+
+extern "C" {
+
+int fhs_version(void) { return 100; }
+
+const char *fhs_last_error(void) { return g_err.c_str(); }
+
+int fhs_filter(int32_t N, double *h_out) {
+  if (N < 1 || N > 8 || !h_out) return fail(FHS_EINVAL, "fhs_filter: N must be in 1..8 and h_out non-null");
+  try {
+    std::vector<long double> h = daubechies(N);
+    for (int i = 0; i < 2 * N; ++i) h_out[i] = static_cast<double>(h[i]);
+  } catch (const std::exception &e) {
+    return fail(FHS_EINVAL, e.what());
+  }
+  return FHS_OK;
+}
+
+int fhs_chi_mean_std(double k, double *mean, double *std_dev) {
+  if (!(k > 0) || !mean || !std_dev) return fail(FHS_EINVAL, "fhs_chi_mean_std: k > 0 and non-null outputs required");
+  chi_mean_std(k, mean, std_dev);
+  return FHS_OK;
+}
+
+int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
+  if (!cfg || !out) return fail(FHS_EINVAL, "fhs_plan_create: null argument");
+  *out = nullptr;
+  const fhs_config c = *cfg;
+  if (c.ny < 1 || c.nx < 1 || c.nchan < 1) return fail(FHS_EINVAL, "image and channel sizes must be positive");
+  if (c.qy < 1 || c.qx < 1 || c.qy > kMaxFacetAxis || c.qx > kMaxFacetAxis)
+    return fail(FHS_EINVAL, "facets per axis must be in 1..64");
+  if (c.qy > c.ny || c.qx > c.nx) return fail(FHS_EINVAL, "more facets than pixels along an axis");
+  if (c.n_sub < 1 || c.nchan % c.n_sub != 0)
+    return fail(FHS_EUNSUPPORTED, "the number of sub-cubes must divide the number of channels");
+  if (c.nchan / c.n_sub > kMaxLc) return fail(FHS_EUNSUPPORTED, "more than 64 channels per sub-cube");
+  if (c.overlap_y < 0 || c.overlap_x < 0) return fail(FHS_EINVAL, "negative overlap");
+  if (c.levels < 1 || c.levels > kMaxLevels) return fail(FHS_EINVAL, "levels must be in 1..6");
+  if (static_cast<int64_t>(c.ny) * c.nx * c.nchan > (int64_t(1) << 40)) return fail(FHS_EUNSUPPORTED, "cube too large");
+
+  fhs_plan *p = new (std::nothrow) fhs_plan();
+  if (!p) return fail(FHS_ENOMEM, "out of host memory");
+  p->cfg = c;
+  p->L = c.nchan;
+  p->C = c.n_sub;
+  p->Lc = c.nchan / c.n_sub;
+  p->Q = c.qy * c.qx;
+  int lcp = 1;
+  while (lcp < p->Lc) lcp *= 2;
+  p->Lcp = lcp;
+  p->lc16 = (p->Lc + 15) / 16 * 16;
+
+  // tiles
+  p->ty.resize(c.qy + 1);
+  p->tx.resize(c.qx + 1);
+  for (int s = 0; s <= c.qy; ++s) p->ty[s] = static_cast<int>(static_cast<int64_t>(s) * c.ny / c.qy);
+  for (int s = 0; s <= c.qx; ++s) p->tx[s] = static_cast<int>(static_cast<int64_t>(s) * c.nx / c.qx);
+  for (int s = 0; s < c.qy; ++s)
+    if (c.qy > 1 && c.overlap_y > p->ty[s + 1] - p->ty[s]) {
+      delete p;
+      return fail(FHS_EINVAL, "overlap_y larger than a tile");
+    }
+  for (int s = 0; s < c.qx; ++s)
+    if (c.qx > 1 && c.overlap_x > p->tx[s + 1] - p->tx[s]) {
+      delete p;
+      return fail(FHS_EINVAL, "overlap_x larger than a tile");
+    }
+
+  // facets, f = c * Q + sy * qx + sx
+  int64_t poff = 0;
+  p->max_rows = 0;
+  for (int cc = 0; cc < p->C; ++cc)
+    for (int sy = 0; sy < c.qy; ++sy)
+      for (int sx = 0; sx < c.qx; ++sx) {
+        fhs_plan::Facet f{};
+        f.c = cc;
+        f.sy = sy;
+        f.sx = sx;
+        f.ty0 = p->ty[sy];
+        f.ty1 = p->ty[sy + 1];
+        f.tx0 = p->tx[sx];
+        f.tx1 = p->tx[sx + 1];
+        f.wy0 = sy > 0 ? f.ty0 - c.overlap_y : f.ty0;
+        f.wx0 = sx > 0 ? f.tx0 - c.overlap_x : f.tx0;
+        f.wy1 = f.ty1;
+        f.wx1 = f.tx1;
+        f.rows = static_cast<int64_t>(f.wy1 - f.wy0) * (f.wx1 - f.wx0);
+        f.poff = poff;
+        poff += f.rows * p->Lc;
+        if (f.rows > p->max_rows) p->max_rows = static_cast<int>(f.rows);
+        p->facets.push_back(f);
+      }
+  p->n_p = poff;
+  p->p_sub = poff / p->C;
+
+  // wavelet bands in storage order
+  int64_t off = 0;
+  for (int b = 0; b < kBases; ++b) {
+    const int taps = 2 * (b + 1);
+    p->ntap[b] = taps;
+    std::vector<long double> h;
+    try {
+      h = daubechies(b + 1);
+    } catch (...) {
+      delete p;
+      return fail(FHS_EINVAL, "filter derivation failed");
+    }
+    for (int m = 0; m < kMaxTap; ++m) {
+      p->h[b][m] = m < taps ? static_cast<float>(h[m]) : 0.0f;
+      // g[m] = (-1)^m h[L-1-m]
+      p->g[b][m] = m < taps ? static_cast<float>(((m & 1) ? -1.0L : 1.0L) * h[taps - 1 - m]) : 0.0f;
+    }
+    p->band_first[b] = static_cast<int64_t>(p->bands.size());
+    int ny = c.ny, nx = c.nx;
+    for (int j = 0; j < c.levels; ++j) {
+      const int Ky = (ny + taps - 1) / 2, Kx = (nx + taps - 1) / 2;
+      p->in_ny[b][j] = ny;
+      p->in_nx[b][j] = nx;
+      p->Ky[b][j] = Ky;
+      p->Kx[b][j] = Kx;
+      for (int s = 0; s < 3; ++s) {
+        p->bands.push_back({Ky, Kx, off, j + 1});
+        off += static_cast<int64_t>(Ky) * Kx;
+      }
+      ny = Ky;
+      nx = Kx;
+    }
+    p->bands.push_back({ny, nx, off, c.levels});
+    off += static_cast<int64_t>(ny) * nx;
+  }
+  p->bands.push_back({c.ny, c.nx, off, 0});
+  off += static_cast<int64_t>(c.ny) * c.nx;
+  p->I = off;
+
+  // workspace: low-low bands of every basis and level but the last, then the
+  // nuclear scratch (partial Gram matrices, K matrices, singular values)
+  int64_t ws = 0;
+  for (int b = 0; b < kBases; ++b)
+    for (int j = 0; j < kMaxLevels; ++j) {
+      p->ws_ll[b][j] = -1;
+      if (j < c.levels - 1) {
+        p->ws_ll[b][j] = ws;
+        ws = align256(ws + static_cast<int64_t>(p->Ky[b][j]) * p->Kx[b][j] * p->L * 4);
+      }
+    }
+  p->gram_chunk_rows = 4096;
+  p->gram_chunks = (p->max_rows + p->gram_chunk_rows - 1) / p->gram_chunk_rows;
+  const int64_t nf = static_cast<int64_t>(p->facets.size());
+  p->ws_gram = ws;
+  ws = align256(ws + nf * p->gram_chunks * p->lc16 * p->lc16 * 8);
+  p->ws_kmat = ws;
+  ws = align256(ws + nf * p->lc16 * p->lc16 * 8);
+  p->ws_sig = ws;
+  ws = align256(ws + nf * p->Lc * 8);
+  p->ws_bytes = ws;
+  *out = p;
+  return FHS_OK;
+}
+
+void fhs_plan_destroy(fhs_plan *plan) {
+  if (!plan) return;
+  if (!plan->prof_events.empty()) prof_release(plan);
+  delete plan;
+}
+
+int fhs_plan_sizes(const fhs_plan *p, fhs_sizes *out) {
+  if (!p || !out) return fail(FHS_EINVAL, "fhs_plan_sizes: null argument");
+  out->n_x = static_cast<int64_t>(p->cfg.ny) * p->cfg.nx * p->L;
+  out->n_p = p->n_p;
+  out->n_coef = p->I;
+  out->n_w = p->I * p->L;
+  out->n_theta = p->I * p->C;
+  out->n_facets = static_cast<int64_t>(p->facets.size());
+  out->n_theta_bar = out->n_facets * p->Lc;
+  out->n_bands = static_cast<int64_t>(p->bands.size());
+  out->workspace_bytes = p->ws_bytes;
+  return FHS_OK;
+}
+
+int fhs_plan_facet(const fhs_plan *p, int32_t f, int64_t out[12]) {
+  if (!p || !out) return fail(FHS_EINVAL, "fhs_plan_facet: null argument");
+  if (f < 0 || f >= static_cast<int32_t>(p->facets.size())) return fail(FHS_EINVAL, "facet index out of range");
+  const auto &F = p->facets[f];
+  const int64_t v[12] = {F.c, F.sy, F.sx, F.ty0, F.ty1, F.tx0, F.tx1, F.wy0, F.wy1, F.wx0, F.wx1, F.poff};
+  std::memcpy(out, v, sizeof(v));
+  return FHS_OK;
+}
+
+int fhs_plan_band(const fhs_plan *p, int32_t k, int64_t out[4]) {
+  if (!p || !out) return fail(FHS_EINVAL, "fhs_plan_band: null argument");
+  if (k < 0 || k >= static_cast<int32_t>(p->bands.size())) return fail(FHS_EINVAL, "band index out of range");
+  const auto &B = p->bands[k];
+  out[0] = B.rows;
+  out[1] = B.cols;
+  out[2] = B.off;
+  out[3] = B.level;
+  return FHS_OK;
+}
+
+int fhs_plan_heuristics(const fhs_plan *p, const double *sigma_bar, double *mu, double *mu_bar) {
+  if (!p || !sigma_bar || !mu || !mu_bar) return fail(FHS_EINVAL, "fhs_plan_heuristics: null argument");
+  double m, s;
+  chi_mean_std(static_cast<double>(p->Lc), &m, &s);
+  for (int c = 0; c < p->C; ++c) {
+    if (!(sigma_bar[c] > 0)) return fail(FHS_EINVAL, "sigma_bar must be positive");
+    mu[c] = sigma_bar[c] * (m + s);
+  }
+  for (size_t f = 0; f < p->facets.size(); ++f) {
+    const double n = static_cast<double>(p->facets[f].rows);
+    const double J = std::min(n, static_cast<double>(p->Lc));
+    mu_bar[f] = sigma_bar[p->facets[f].c] * std::sqrt(n * p->Lc / J);
+  }
+  return FHS_OK;
+}
+
+int fhs_plan_set_workspace(fhs_plan *p, void *dev_ptr, int64_t bytes) {
+  if (!p) return fail(FHS_EINVAL, "fhs_plan_set_workspace: null plan");
+  if (!dev_ptr || bytes < p->ws_bytes)
+    return fail(FHS_EINVAL, "workspace missing or smaller than fhs_sizes.workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0) return fail(FHS_EINVAL, "workspace must be 256-byte aligned");
+  p->ws = dev_ptr;
+  p->ws_given = bytes;
+  return FHS_OK;
+}
+
+}  // extern "C"

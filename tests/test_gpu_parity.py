@@ -1,0 +1,180 @@
+"""GPU parity of every C-ABI compute call against the FP64 oracle.
+
+Same seeded inputs on both sides (the oracle reads the float32 arrays promoted
+to float64).  Bar: relative L2 error <= 1e-5 per output array (FP32 path; the
+nuclear update accumulates in FP64), and an element-wise bound of 1e-4 of the
+array's largest magnitude; integer-like invariants (zero in, zero out;
+determinism) are exact.  Cases span several workgroup tiles, ragged sizes,
+odd channel counts (Jacobi padding), interleaved sub-cubes, one facet,
+zero overlap, 64 channels per sub-cube, shallow decompositions and warm /
+signed inputs.
+"""
+import numpy as np
+import pytest
+
+from fhs_cases import Problem, log, max_rel, rel_l2
+from oracle import sara, step
+
+torch = pytest.importorskip("torch")
+fhs = pytest.importorskip("paper_2003_07358_amd")
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+ELEM = 1e-4
+
+CASES = {
+    "cfg1_256x256x20_q2x2_o32": dict(ny=256, nx=256, L=20, qy=2, qx=2, oy=32, ox=32),
+    "ragged_101x77x6_q3x2_c2": dict(ny=101, nx=77, L=6, qy=3, qx=2, C=2, oy=7, ox=5, blobs=12),
+    "lc64_70x45x64_q2x1": dict(ny=70, nx=45, L=64, qy=2, qx=1, oy=9, ox=0, blobs=8),
+    "lc5_odd_48x40x5_q1x1": dict(ny=48, nx=40, L=5, blobs=6),
+    "tiny_7x9x3_levels2": dict(ny=7, nx=9, L=3, levels=2, blobs=2),
+    "c4_64x64x12_q4x4_o0": dict(ny=64, nx=64, L=12, qy=4, qx=4, C=4, blobs=10),
+}
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def make(name, **kw):
+    args = dict(CASES[name])
+    args.update(kw)
+    log(f"[case] {name} {kw}")
+    pb = Problem(**args)
+    plan = fhs.Plan(*pb.cfg).attach_workspace()
+    return pb, plan
+
+
+def check(name, got, ref, tol=TOL):
+    e, m = rel_l2(got, ref), max_rel(got, ref)
+    log(f"    {name}: rel_l2={e:.3e} max_rel={m:.3e}")
+    assert e <= tol, (name, e)
+    assert m <= ELEM, (name, m)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sara_analysis(name):
+    pb, plan = make(name)
+    w = torch.empty(plan.sizes["n_w"], dtype=torch.float32, device="cuda")
+    plan.sara_analysis(dev(pb.X), w)
+    check("Psi^dagger x", host(w).reshape(pb.I, pb.L), pb.oracle_analysis())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sara_synthesis(name):
+    pb, plan = make(name)
+    rng = np.random.default_rng(7)
+    wv = rng.standard_normal((pb.I, pb.L)).astype(np.float32)
+    x0 = rng.standard_normal((pb.ny, pb.nx, pb.L)).astype(np.float32)
+    xt = dev(x0)
+    plan.sara_synthesis(dev(wv), xt, alpha=1.5, beta=0.5)
+    ref = 0.5 * x0.astype(np.float64)
+    for c, ch in enumerate(step.subcube_channels(pb.L, pb.C)):
+        part = wv[:, c * pb.Lc:(c + 1) * pb.Lc].astype(np.float64)
+        ref[..., ch] += 1.5 * sara.synthesis(sara.unflatten(part, pb.ny, pb.nx, pb.levels), pb.ny, pb.nx,
+                                             pb.levels)
+    check("beta x + alpha Psi w", host(xt), ref)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("warm", [False, True])
+def test_l21_dual_update(name, warm):
+    pb, plan = make(name, warm=warm)
+    kappa = 1.0 if not warm else 0.8
+    w = dev(pb.W_flat())
+    g0 = np.random.default_rng(3).standard_normal((pb.ny, pb.nx, pb.L)).astype(np.float32)
+    g = dev(g0)
+    beta = 0.25 if warm else 0.0
+    plan.l21_dual_update(dev(pb.X), w, dev(pb.theta_flat()), dev(pb.mu), kappa, g, beta)
+    Wn, G = pb.oracle_l21(kappa)
+    check("W+", host(w), np.concatenate(Wn, axis=1).reshape(-1))
+    check("beta g + kappa Psi W+", host(g), beta * g0.astype(np.float64) + G)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("warm", [False, True])
+def test_nuclear_dual_update(name, warm):
+    pb, plan = make(name, warm=warm)
+    zeta = 1.0 if not warm else 1.3
+    p = dev(pb.P_flat())
+    g0 = np.random.default_rng(4).standard_normal((pb.ny, pb.nx, pb.L)).astype(np.float32)
+    g = dev(g0)
+    beta = 0.5 if warm else 0.0
+    plan.nuclear_dual_update(dev(pb.X), p, dev(pb.theta_bar_flat()), dev(pb.mu_bar_flat()), zeta, g, beta)
+    Pn, G = pb.oracle_nuclear(zeta)
+    ref = np.concatenate([q.reshape(-1) for row in Pn for q in row])
+    check("P+", host(p), ref)
+    check("beta g + zeta sum S~^T D P+", host(g), beta * g0.astype(np.float64) + G)
+
+
+@pytest.mark.parametrize("variant", ["plain", "signed"])
+@pytest.mark.parametrize("warm", [False, True])
+def test_facet_prox_step_cfg1(variant, warm):
+    pb, plan = make("cfg1_256x256x20_q2x2_o32", variant=variant, warm=warm)
+    p, w = dev(pb.P_flat()), dev(pb.W_flat())
+    g = torch.full((plan.sizes["n_x"],), float("nan"), device="cuda")   # overwritten, never read
+    plan.facet_prox_step(dev(pb.X), p, w, dev(pb.theta_flat()), dev(pb.theta_bar_flat()), dev(pb.mu),
+                         dev(pb.mu_bar_flat()), 1.0, 1.0, g)
+    Pn, Wn, G = pb.oracle_step()
+    check("P+", host(p), np.concatenate([q.reshape(-1) for row in Pn for q in row]))
+    check("W+", host(w), np.concatenate(Wn, axis=1).reshape(-1))
+    check("G", host(g), G.reshape(-1))
+
+
+def test_reweight():
+    pb, plan = make("ragged_101x77x6_q3x2_c2")
+    from oracle import heuristics
+    ups = np.array([0.05, 0.02])
+    upb = np.linspace(0.5, 1.5, pb.C * pb.geom.Q)
+    th = torch.empty(plan.sizes["n_theta"], dtype=torch.float32, device="cuda")
+    tb = torch.empty(plan.sizes["n_theta_bar"], dtype=torch.float64, device="cuda")
+    plan.reweight(dev(pb.X), dev(ups), dev(upb), th, tb)
+    ref_t = np.concatenate(heuristics.l21_weights(pb.X, ups, pb.levels, pb.C))
+    ref_b = heuristics.nuclear_weights(pb.X, pb.geom, upb.reshape(pb.C, -1), pb.C)
+    check("theta", host(th), ref_t)
+    check("theta_bar", host(tb), np.concatenate([t for row in ref_b for t in row]), tol=1e-8)
+
+
+def test_zero_input_gives_zero():
+    pb, plan = make("cfg1_256x256x20_q2x2_o32", zero=True)
+    p, w = dev(pb.P_flat()), dev(pb.W_flat())
+    g = torch.full((plan.sizes["n_x"],), 7.0, device="cuda")
+    plan.facet_prox_step(dev(pb.X), p, w, dev(pb.theta_flat()), dev(pb.theta_bar_flat()), dev(pb.mu),
+                         dev(pb.mu_bar_flat()), 1.0, 1.0, g)
+    assert np.all(host(p) == 0) and np.all(host(w) == 0) and np.all(host(g) == 0)
+
+
+def test_bitwise_deterministic():
+    pb, plan = make("ragged_101x77x6_q3x2_c2", warm=True)
+    outs = []
+    for _ in range(2):
+        p, w = dev(pb.P_flat()), dev(pb.W_flat())
+        g = torch.empty(plan.sizes["n_x"], device="cuda")
+        plan.facet_prox_step(dev(pb.X), p, w, dev(pb.theta_flat()), dev(pb.theta_bar_flat()), dev(pb.mu),
+                             dev(pb.mu_bar_flat()), 1.0, 1.0, g)
+        outs.append((host(p), host(w), host(g)))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.slow
+def test_facet_prox_step_cfg2_full():
+    """1024 x 2048 x 20, 4 x 4 facets, 64-px overlap: the full FP64 oracle."""
+    log("[case] cfg2_1024x2048x20_q4x4_o64 full oracle")
+    pb = Problem(1024, 2048, 20, 4, 4, 1, 64, 64, 4, seed=2, blobs=50)
+    plan = fhs.Plan(*pb.cfg).attach_workspace()
+    p, w = dev(pb.P_flat()), dev(pb.W_flat())
+    g = torch.empty(plan.sizes["n_x"], device="cuda")
+    plan.facet_prox_step(dev(pb.X), p, w, dev(pb.theta_flat()), dev(pb.theta_bar_flat()), dev(pb.mu),
+                         dev(pb.mu_bar_flat()), 1.0, 1.0, g)
+    gp, gw, gg = host(p), host(w), host(g)
+    log("    gpu done; running oracle")
+    Pn, Wn, G = pb.oracle_step()
+    check("P+", gp, np.concatenate([q.reshape(-1) for row in Pn for q in row]))
+    check("W+", gw, np.concatenate(Wn, axis=1).reshape(-1))
+    check("G", gg, G.reshape(-1))
