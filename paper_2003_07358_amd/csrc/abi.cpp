@@ -14,7 +14,8 @@ namespace {
 constexpr int kTkyAna = 64;   // coefficient rows per analysis workgroup
 constexpr int kTySyn = 64;    // output rows per synthesis workgroup (levels >= 2)
 constexpr int kTyFinal = 128; // output rows per final synthesis workgroup
-constexpr int kE = 1;         // coefficient columns per analysis thread
+constexpr int kDiracE = 4;    // pixels in flight per thread in the Dirac part of the analysis
+constexpr int kMaxDiracWg = 2048;
 
 int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
@@ -46,7 +47,7 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
                  int mode, void *stream) {
   int tkx1, nth;
   if (int rc = thread_cfg(p, &tkx1, &nth)) return rc;
-  const int TKX = kE * tkx1;
+  const int TKX = tkx1;
   const int levels = p->cfg.levels;
   for (int j = 0; j < levels; ++j) {
     AnaArgs a;
@@ -89,13 +90,15 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       D.in_ny = p->cfg.ny;
       D.in_nx = p->cfg.nx;
       D.off[0] = dirac_off(p);
-      prefix += ceil_div(static_cast<int64_t>(p->cfg.ny) * p->cfg.nx, TKX);
+      // grid-stride workgroups for the Dirac band (kDiracE pixels in flight per thread)
+      D.strips = std::max(1, std::min(kMaxDiracWg, ceil_div(static_cast<int64_t>(p->cfg.ny) * p->cfg.nx,
+                                                            static_cast<int64_t>(kDiracE) * TKX)));
+      prefix += D.strips;
     }
     a.wg_prefix[kBases + 1] = prefix;
-    const int lds = (2 * TKX + kMaxTap - 2) * p->L;
     const int kid = j == 0 ? FHS_K_ANALYSIS_L1 : FHS_K_ANALYSIS;
     prof_begin(p, kid, stream);
-    const int rc = launch_analysis(a, nth, lds, kE, j == 0, stream);
+    const int rc = launch_analysis(a, nth, j == 0, stream);
     prof_end(p, kid, stream);
     if (rc) return rc;
   }
@@ -135,9 +138,8 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
       prefix += B.strips * B.yblocks;
     }
     s.wg_prefix[kBases] = prefix;
-    const int lds = 4 * (tk + kMaxTap / 2 - 1) * L;
     prof_begin(p, FHS_K_SYNTHESIS, stream);
-    const int rc = launch_synthesis(s, nth, lds, stream);
+    const int rc = launch_synthesis(s, nth, stream);
     prof_end(p, FHS_K_SYNTHESIS, stream);
     if (rc) return rc;
   }

@@ -111,8 +111,8 @@ struct GatherArgs {
 };
 
 // ---------------------------------------------------------------- launchers
-int launch_analysis(const AnaArgs &a, int nthreads, int lds_floats, int E, bool first, void *stream);
-int launch_synthesis(const SynArgs &a, int nthreads, int lds_floats, void *stream);
+int launch_analysis(const AnaArgs &a, int nthreads, bool first, void *stream);
+int launch_synthesis(const SynArgs &a, int nthreads, void *stream);
 int launch_synthesis_final(const SynFinalArgs &a, int nthreads, int group, void *stream);
 int launch_nuc_gram(const NucArgs &a, int nfacets, void *stream);
 int launch_nuc_eig(const NucArgs &a, int nfacets, void *stream);

@@ -28,6 +28,13 @@ int main(int argc, char **argv) {
       const long double gm = ((m & 1) ? -1.0L : 1.0L) * h[L - 1 - m];
       std::fprintf(f, "%s%.9ef", m ? ", " : "", static_cast<double>(static_cast<float>(gm)));
     }
+    std::fprintf(f, "};\n  static constexpr double hd[%d] = {", L);
+    for (int m = 0; m < L; ++m) std::fprintf(f, "%s%.17e", m ? ", " : "", static_cast<double>(h[m]));
+    std::fprintf(f, "};\n  static constexpr double gd[%d] = {", L);
+    for (int m = 0; m < L; ++m) {
+      const long double gm = ((m & 1) ? -1.0L : 1.0L) * h[L - 1 - m];
+      std::fprintf(f, "%s%.17e", m ? ", " : "", static_cast<double>(gm));
+    }
     std::fprintf(f, "};\n};\n");
   }
   std::fprintf(f, "}  // namespace fhs\n");

@@ -1,0 +1,91 @@
+// Device helpers shared by the wavelet kernels: staging contiguous HBM
+// segments into LDS with buffer loads whose destination is LDS, and the
+// channel-segment reduction used by the l21 row norm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+typedef int fhs_int32x4 __attribute__((ext_vector_type(4)));
+
+// Buffer load whose data goes to LDS: lane i of the wave writes `size` bytes at
+// lds + i * size (lds must be wave-uniform).  Out-of-range offsets (buffer range
+// checking) write zeros.
+__device__ void fhs_raw_buffer_load_lds(fhs_int32x4 rsrc, __attribute__((address_space(3))) unsigned int *lds,
+                                        int size, int voffset, int soffset, int offset,
+                                        int aux) __asm("llvm.amdgcn.raw.buffer.load.lds");
+
+namespace fhs {
+
+__device__ __forceinline__ fhs_int32x4 buffer_rsrc(const void *base, unsigned bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  fhs_int32x4 r;
+  r.x = static_cast<int>(a & 0xffffffffu);
+  r.y = static_cast<int>((a >> 32) & 0xffffu);  // stride 0
+  r.z = static_cast<int>(bytes);                 // range in bytes
+  r.w = 0x00020000;                              // gfx9-family raw-buffer word 3
+  return r;
+}
+
+__device__ __forceinline__ int round_up(int n, int m) { return (n + m - 1) / m * m; }
+
+// One wave copies floats [seg0, seg0 + n) of `row` (zero outside [0, rowlen),
+// or everywhere when !valid) into dst[0 .. n); dst must hold round_up(n, 64)
+// floats (the lanes past n write zeros there).
+__device__ __forceinline__ void wave_copy_row(const float *row, int64_t rowlen, int64_t seg0, int n, bool valid,
+                                              float *dst) {
+  const fhs_int32x4 rsrc = buffer_rsrc(row, valid ? static_cast<unsigned>(rowlen * 4) : 0u);
+  const int lane = threadIdx.x & 63;
+  for (int base = 0; base < n; base += 64) {
+    const int i = base + lane;
+    const int64_t gi = seg0 + i;
+    const int voff = (i < n && gi >= 0 && gi < rowlen) ? static_cast<int>(gi * 4) : static_cast<int>(0x80000000u);
+    __attribute__((address_space(3))) unsigned int *l =
+        reinterpret_cast<__attribute__((address_space(3))) unsigned int *>(reinterpret_cast<uintptr_t>(dst + base));
+    fhs_raw_buffer_load_lds(rsrc, l, 4, voff, 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+// Waves with all 64 lanes present: only these issue LDS copies (a partial wave
+// would leave the slots of its missing lanes unwritten).  The launchers use
+// at least 64 threads per workgroup.
+__device__ __forceinline__ int full_wave_count() { return blockDim.x >> 6; }
+
+// All of this thread's outstanding vector-memory operations complete (the
+// LDS copies included), then a workgroup barrier.
+__device__ __forceinline__ void wait_loads_and_sync() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+}
+
+__device__ __forceinline__ void drain_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Sum over the aligned segment of `lcp` lanes (a power of two dividing 64),
+// every lane of the segment receiving the sum.  Butterfly with cross-lane
+// moves that stay in the VALU where possible: DPP quad permutations (lane ^ 1,
+// lane ^ 2), DPP half-row and row mirrors (which pair the two halves of 8 and
+// of 16 lanes), a ds_swizzle xor 16 and, for 64 lanes, a bpermute.
+__device__ __forceinline__ float dpp_add(float v, int ctrl_tag) {
+  int o;
+  switch (ctrl_tag) {
+    case 0: o = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false); break;   // quad [1,0,3,2]
+    case 1: o = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false); break;   // quad [2,3,0,1]
+    case 2: o = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false); break;  // row half mirror
+    default: o = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false); break; // row mirror
+  }
+  return v + __int_as_float(o);
+}
+
+__device__ __forceinline__ float seg_sum(float v, int lcp) {
+  if (lcp >= 2) v = dpp_add(v, 0);
+  if (lcp >= 4) v = dpp_add(v, 1);
+  if (lcp >= 8) v = dpp_add(v, 2);
+  if (lcp >= 16) v = dpp_add(v, 3);
+  if (lcp >= 32) v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));  // lane ^ 16
+  if (lcp >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+}  // namespace fhs

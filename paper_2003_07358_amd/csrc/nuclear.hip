@@ -58,21 +58,35 @@ __device__ __forceinline__ double ramp(int i, int s, int Q, int o, int len) {
 }
 
 // Stages rows [r0, r0 + kRB) of Z (FP64, zero padded to W columns) into LDS.
+// The first kRB threads resolve each row's pixel and window weight once
+// (rinfo_pix / rinfo_d, kRB entries each); every element then needs no
+// division.  The caller synchronises before and after.
 template <int W>
-__device__ __forceinline__ void stage_z(const NucArgs &A, const FacetView &F, int64_t r0, int64_t r_end, double *zs) {
+__device__ __forceinline__ void stage_z(const NucArgs &A, const FacetView &F, int64_t r0, int64_t r_end, double *zs,
+                                       int64_t *rinfo_pix, double *rinfo_d) {
   const NucGeom &g = A.g;
+  if (threadIdx.x < kRB) {
+    const int64_t r = r0 + threadIdx.x;
+    int64_t pix = -1;
+    double d = 0.0;
+    if (r < r_end) {
+      const int ri = static_cast<int>(r);  // facet rows fit in 32 bits
+      const int yy = ri / F.hx, xx = ri - yy * F.hx;
+      d = ramp(yy, F.sy, g.qy, g.oy, F.hy) * ramp(xx, F.sx, g.qx, g.ox, F.hx);
+      pix = static_cast<int64_t>(F.wy0 + yy) * g.nx + (F.wx0 + xx);
+    }
+    rinfo_pix[threadIdx.x] = pix;
+    rinfo_d[threadIdx.x] = d;
+  }
+  __syncthreads();
   for (int idx = threadIdx.x; idx < kRB * W; idx += blockDim.x) {
-    const int rr = idx / W, l = idx - (idx / W) * W;
-    const int64_t r = r0 + rr;
+    const int rr = idx / W, l = idx % W;
+    const int64_t pix = rinfo_pix[rr];
     double z = 0.0;
-    if (r < r_end && l < g.Lc) {
-      const int yy = static_cast<int>(r / F.hx);
-      const int xx = static_cast<int>(r - static_cast<int64_t>(yy) * F.hx);
-      const double d = ramp(yy, F.sy, g.qy, g.oy, F.hy) * ramp(xx, F.sx, g.qx, g.ox, F.hx);
-      const int64_t pix = static_cast<int64_t>(F.wy0 + yy) * g.nx + (F.wx0 + xx);
+    if (pix >= 0 && l < g.Lc) {
       const double xv = static_cast<double>(A.x[pix * g.L + F.c + l * g.C]);
-      const double pv = A.p ? static_cast<double>(A.p[F.poff + r * g.Lc + l]) : 0.0;
-      z = pv + d * xv;
+      const double pv = A.p ? static_cast<double>(A.p[F.poff + (r0 + rr) * g.Lc + l]) : 0.0;
+      z = pv + rinfo_d[rr] * xv;
     }
     zs[rr * (W + 1) + l] = z;
   }
@@ -84,6 +98,8 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
   constexpr int NPAIR = NB * (NB + 1) / 2;
   constexpr int PPW = (NPAIR + 3) / 4;
   __shared__ double zs[kRB * (W + 1)];
+  __shared__ int64_t rinfo_pix[kRB];
+  __shared__ double rinfo_d[kRB];
   const int f = blockIdx.y, chunk = blockIdx.x;
   const FacetView F = facet_view(A.g, f);
   const int64_t r_begin = static_cast<int64_t>(chunk) * A.chunk_rows;
@@ -113,7 +129,7 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
 
   for (int64_t rb = r_begin; rb < r_end; rb += kRB) {
     __syncthreads();
-    stage_z<W>(A, F, rb, r_end, zs);
+    stage_z<W>(A, F, rb, r_end, zs, rinfo_pix, rinfo_d);
     __syncthreads();
 #pragma unroll 4
     for (int k4 = 0; k4 < kRB / 4; ++k4) {
@@ -129,7 +145,8 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
     if (act[t])
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = 16 * bi[t] + 4 * (ln / 16) + v, j = 16 * bj[t] + ln % 16;
+        // v_mfma_f64_16x16x4f64 result layout: lane holds D[4 v + lane / 16][lane % 16]
+        const int i = 16 * bi[t] + 4 * v + ln / 16, j = 16 * bj[t] + ln % 16;
         out[i * A.lc16 + j] = acc[t][v];
       }
 }
@@ -273,6 +290,8 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
   constexpr int W = NB * 16;
   __shared__ double Ks[W * (W + 1)];
   __shared__ double zs[kRB * (W + 1)];
+  __shared__ int64_t rinfo_pix[kRB];
+  __shared__ double rinfo_d[kRB];
   const int f = blockIdx.y;
   const FacetView F = facet_view(A.g, f);
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kRB;
@@ -282,7 +301,7 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
     const int i = idx / W, j = idx - (idx / W) * W;
     Ks[i * (W + 1) + j] = K[i * A.lc16 + j];
   }
-  stage_z<W>(A, F, r0, F.rows, zs);
+  stage_z<W>(A, F, r0, F.rows, zs, rinfo_pix, rinfo_d);
   __syncthreads();
   const int wave = threadIdx.x / 64, ln = threadIdx.x % 64;
   const int nb = wave;  // 16-row block of the 64 staged rows
@@ -301,40 +320,64 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
     if (r < F.rows) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int j = 16 * mb + 4 * (ln / 16) + v;
+        const int j = 16 * mb + 4 * v + ln / 16;
         if (j < A.g.Lc) A.p[F.poff + r * A.g.Lc + j] = static_cast<float>(acc[v]);
       }
     }
   }
 }
 
+// Thread = one pixel and up to 4 channels; all loads of the thread (up to 4
+// facets x 4 channels of P, and the previous gradient) are independent.
 __global__ void __launch_bounds__(256) nuc_gather_kernel(GatherArgs A) {
   const NucGeom &g = A.g;
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t total = static_cast<int64_t>(g.ny) * g.nx * g.L;
-  if (idx >= total) return;
-  const int64_t pix = idx / g.L;
-  const int ch = static_cast<int>(idx - pix * g.L);
+  const int ngrp = (g.L + 3) / 4;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t npix = static_cast<int64_t>(g.ny) * g.nx;
+  const int64_t pix = t / ngrp;
+  if (pix >= npix) return;
+  const int ch0 = 4 * static_cast<int>(t - pix * ngrp);
   const int y = static_cast<int>(pix / g.nx), x = static_cast<int>(pix - static_cast<int64_t>(y) * g.nx);
-  const int c = ch % g.C, l = ch / g.C;
   const int sy0 = static_cast<int>((static_cast<int64_t>(y + 1) * g.qy + g.ny - 1) / g.ny) - 1;
   const int sx0 = static_cast<int>((static_cast<int64_t>(x + 1) * g.qx + g.nx - 1) / g.nx) - 1;
-  const bool ny2 = sy0 + 1 < g.qy && y >= g.ty[sy0 + 1] - g.oy;
-  const bool nx2 = sx0 + 1 < g.qx && x >= g.tx[sx0 + 1] - g.ox;
-  double sum = 0.0;
-  for (int dy = 0; dy < 2; ++dy) {
-    if (dy == 1 && !ny2) break;
-    for (int dx = 0; dx < 2; ++dx) {
-      if (dx == 1 && !nx2) break;
-      const int f = c * g.qy * g.qx + (sy0 + dy) * g.qx + (sx0 + dx);
-      const FacetView F = facet_view(g, f);
+  const int ncy = (sy0 + 1 < g.qy && y >= g.ty[sy0 + 1] - g.oy) ? 2 : 1;
+  const int ncx = (sx0 + 1 < g.qx && x >= g.tx[sx0 + 1] - g.ox) ? 2 : 1;
+  // the (at most four) covering facets of sub-cube 0: weight and P row offset
+  double dk[4];
+  int64_t rk[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int dy = k >> 1, dx = k & 1;
+    dk[k] = 0.0;
+    rk[k] = 0;
+    if (dy < ncy && dx < ncx) {
+      const FacetView F = facet_view(g, (sy0 + dy) * g.qx + (sx0 + dx));
       const int yy = y - F.wy0, xx = x - F.wx0;
-      const double d = ramp(yy, F.sy, g.qy, g.oy, F.hy) * ramp(xx, F.sx, g.qx, g.ox, F.hx);
-      sum += d * static_cast<double>(A.p[F.poff + (static_cast<int64_t>(yy) * F.hx + xx) * g.Lc + l]);
+      dk[k] = ramp(yy, F.sy, g.qy, g.oy, F.hy) * ramp(xx, F.sx, g.qx, g.ox, F.hx);
+      rk[k] = F.poff + (static_cast<int64_t>(yy) * F.hx + xx) * g.Lc;
     }
   }
-  const float v = static_cast<float>(A.zeta * sum);
-  A.grad[idx] = A.beta != 0.0f ? fmaf(A.beta, A.grad[idx], v) : v;
+  float pv[4][4], gv[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int ch = ch0 + e;
+    const bool ok = ch < g.L;
+    const int c = ch % g.C, l = ch / g.C;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pv[e][k] = (ok && dk[k] != 0.0) ? A.p[c * g.p_sub + rk[k] + l] : 0.0f;
+    gv[e] = (ok && A.beta != 0.0f) ? A.grad[pix * g.L + ch] : 0.0f;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int ch = ch0 + e;
+    if (ch < g.L) {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sum += dk[k] * static_cast<double>(pv[e][k]);
+      const float v = static_cast<float>(A.zeta * sum);
+      A.grad[pix * g.L + ch] = A.beta != 0.0f ? fmaf(A.beta, gv[e], v) : v;
+    }
+  }
 }
 
 static int check_launch(const char *what) {
@@ -375,7 +418,7 @@ int launch_nuc_recon(const NucArgs &a, int nfacets, int rowblocks, void *stream)
 }
 
 int launch_nuc_gather(const GatherArgs &a, void *stream) {
-  const int64_t total = static_cast<int64_t>(a.g.ny) * a.g.nx * a.g.L;
+  const int64_t total = static_cast<int64_t>(a.g.ny) * a.g.nx * ((a.g.L + 3) / 4);
   const int64_t blocks = (total + 255) / 256;
   hipLaunchKernelGGL(nuc_gather_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
                      static_cast<hipStream_t>(stream), a);

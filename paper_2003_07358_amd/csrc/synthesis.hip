@@ -1,0 +1,395 @@
+// SARA synthesis Psi w for gfx950: the exact adjoint of the analysis (Sec.
+// 2.3.1; Alg. 2 step alg:step:end_facet-l21 summed over facets and the kappa
+// term of step alg:step:aggregate).
+//
+// One level of the adjoint: an output sample x = 2k + px receives
+// sum_{i < L/2} f[2i + 1 - px] c[k + i], so a thread owning coefficient column k
+// produces output columns 2k and 2k+1, and output rows 2k' and 2k'+1 come from
+// coefficient rows k' .. k' + L/2 - 1, whose horizontal adjoints are kept in a
+// per-thread register ring.
+//
+// Levels >= 2 run one basis per workgroup and write the low-low band of the
+// level above into the workspace.  Level 1 runs a group of bases per
+// workgroup and sums them (and the Dirac basis) into the image in a fixed
+// order: deterministic, no atomics.
+//
+// Memory pipeline: coefficient rows are grouped into phases of P rows whose
+// four band segments are copied HBM -> LDS by buffer loads with LDS
+// destination one phase ahead (double-buffered LDS), one barrier per phase;
+// the values read at the outputs (Dirac band, previous image) are loaded into
+// registers one phase ahead.
+#include <hip/hip_runtime.h>
+
+#include "fhs_filters.h"
+#include "fhs_internal.h"
+#include "lds_stage.h"
+
+#ifndef FHS_FINAL_SPLIT
+#define FHS_FINAL_SPLIT 4
+#endif
+#ifndef FHS_FINAL_WPE
+#define FHS_FINAL_WPE 2
+#endif
+
+namespace fhs {
+
+namespace {
+
+// Segment j of a phase = (row j / 4, band j % 4): copy it into dst + j * segp.
+__device__ __forceinline__ void issue_band_rows(const SynBand &B, int k0, int nrows, int kx0, int segn, int segp,
+                                                int L, float *dst) {
+  const int64_t rowlen = static_cast<int64_t>(B.Kx) * L;
+  const int64_t c0 = static_cast<int64_t>(kx0) * L;
+  const int wv = wave_id(), nwv = full_wave_count();
+  if (wv >= nwv) return;
+#pragma unroll
+  for (int band = 0; band < 4; ++band) {
+    const float *src = band == 0 ? B.ll : band == 1 ? B.lh : band == 2 ? B.hl : B.hh;
+    for (int row = 0; row < nrows; ++row) {
+      const int j = 4 * row + band;
+      if (j % nwv != wv) continue;
+      const int k = k0 + row;
+      const bool kv = k >= 0 && k < B.Ky;
+      wave_copy_row(src + (kv ? static_cast<int64_t>(k) * rowlen : 0), rowlen, c0, segn, kv, dst + j * segp);
+    }
+  }
+}
+
+// Horizontal adjoint of one staged coefficient row (bands at buf + b * segp)
+// for both output parities.
+template <int NTAP>
+__device__ __forceinline__ void xadj(const float *buf, int segp, int off, int L, float &lo0, float &lo1, float &hi0,
+                                     float &hi1) {
+  using T = Taps<NTAP>;
+  constexpr int H = NTAP / 2;
+  lo0 = lo1 = hi0 = hi1 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const float cll = buf[off + i * L];
+    const float clh = buf[segp + off + i * L];
+    const float chl = buf[2 * segp + off + i * L];
+    const float chh = buf[3 * segp + off + i * L];
+    // even output column (px = 0): taps 2i+1 ; odd (px = 1): taps 2i
+    lo0 = fmaf(T::h[2 * i + 1], cll, fmaf(T::g[2 * i + 1], clh, lo0));
+    lo1 = fmaf(T::h[2 * i], cll, fmaf(T::g[2 * i], clh, lo1));
+    hi0 = fmaf(T::h[2 * i + 1], chl, fmaf(T::g[2 * i + 1], chh, hi0));
+    hi1 = fmaf(T::h[2 * i], chl, fmaf(T::g[2 * i], chh, hi1));
+  }
+}
+
+template <int NTAP>
+struct Ring {
+  float lo[2][NTAP / 2], hi[2][NTAP / 2];  // [output parity][coefficient row, oldest first]
+};
+
+template <int NTAP>
+__device__ __forceinline__ void ring_zero(Ring<NTAP> &R) {
+#pragma unroll
+  for (int i = 0; i < NTAP / 2; ++i) R.lo[0][i] = R.lo[1][i] = R.hi[0][i] = R.hi[1][i] = 0.0f;
+}
+
+template <int NTAP>
+__device__ __forceinline__ void ring_push(const float *buf, int segp, int off, int L, Ring<NTAP> &R) {
+  constexpr int H = NTAP / 2;
+#pragma unroll
+  for (int i = 0; i + 1 < H; ++i) {
+    R.lo[0][i] = R.lo[0][i + 1];
+    R.lo[1][i] = R.lo[1][i + 1];
+    R.hi[0][i] = R.hi[0][i + 1];
+    R.hi[1][i] = R.hi[1][i + 1];
+  }
+  xadj<NTAP>(buf, segp, off, L, R.lo[0][H - 1], R.lo[1][H - 1], R.hi[0][H - 1], R.hi[1][H - 1]);
+}
+
+// Vertical adjoint: adds the 2 x 2 outputs (rows 2k', 2k'+1) of the ring.
+template <int NTAP>
+__device__ __forceinline__ void ring_out(const Ring<NTAP> &R, float acc[2][2]) {
+  using T = Taps<NTAP>;
+  constexpr int H = NTAP / 2;
+#pragma unroll
+  for (int py = 0; py < 2; ++py)
+#pragma unroll
+    for (int px = 0; px < 2; ++px) {
+      float v = 0.0f;
+#pragma unroll
+      for (int i = 0; i < H; ++i) {
+        const int m = 2 * i + 1 - py;
+        v = fmaf(T::h[m], R.lo[px][i], fmaf(T::g[m], R.hi[px][i], v));
+      }
+      acc[py][px] += v;
+    }
+}
+
+// ---------------------------------------------------------------- levels >= 2
+
+template <int NTAP, int P>
+__device__ __forceinline__ void syn_basis(const SynArgs &A, const SynBand &B, int wg, float *smem) {
+  constexpr int H = NTAP / 2;
+  const int L = A.L, Lcp = A.Lcp, C = A.C, Lc = A.Lc;
+  const int tid = threadIdx.x;
+  const int lane = tid % Lcp, grp = tid / Lcp, c = grp % C, kq = grp / C;
+  const bool lv = lane < Lc;
+  const int p = c * Lc + lane;
+  const int strip = wg % B.strips, yb = wg / B.strips;
+  const int kx0 = strip * A.tk;
+  const int y0 = yb * A.ty;
+  const int y1 = min(y0 + A.ty, B.ny);
+  const int segn = (A.tk + H - 1) * L;
+  const int segp = round_up(segn, 64);
+  const int ks = y0 / 2;
+  const int nout = (y1 - 1) / 2 - ks + 1;
+  const int nk = nout + H - 1;
+  const int nph = (nk + P - 1) / P;
+  const int off = kq * L + p;
+  const int x = 2 * (kx0 + kq);
+
+  Ring<NTAP> R;
+  ring_zero(R);
+  issue_band_rows(B, ks, P, kx0, segn, segp, L, smem);
+  for (int ph = 0; ph < nph; ++ph) {
+    wait_loads_and_sync();
+    if (ph + 1 < nph) issue_band_rows(B, ks + (ph + 1) * P, P, kx0, segn, segp, L, smem + ((ph + 1) & 1) * 4 * P * segp);
+    const float *buf = smem + (ph & 1) * 4 * P * segp;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int r = ph * P + k;
+      if (r < nk) {
+        ring_push<NTAP>(buf + 4 * k * segp, segp, off, L, R);
+        if (r >= H - 1) {
+          const int kp = ks + r - (H - 1);
+          float acc[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
+          ring_out<NTAP>(R, acc);
+#pragma unroll
+          for (int py = 0; py < 2; ++py) {
+            const int y = 2 * kp + py;
+#pragma unroll
+            for (int px = 0; px < 2; ++px)
+              if (lv && y < y1 && x + px < B.nx)
+                B.out[(static_cast<int64_t>(y) * B.nx + x + px) * L + p] = acc[py][px];
+          }
+        }
+      }
+    }
+  }
+  drain_loads();
+}
+
+}  // namespace
+
+template <int P>
+__global__ void __launch_bounds__(256) syn_kernel(SynArgs A) {
+  extern __shared__ float smem[];
+  const int id = blockIdx.x;
+  int b = 0;
+  while (b < kBases - 1 && id >= A.wg_prefix[b + 1]) ++b;
+  const int wg = id - A.wg_prefix[b];
+  switch (b) {
+    case 0: syn_basis<2, P>(A, A.b[0], wg, smem); break;
+    case 1: syn_basis<4, P>(A, A.b[1], wg, smem); break;
+    case 2: syn_basis<6, P>(A, A.b[2], wg, smem); break;
+    case 3: syn_basis<8, P>(A, A.b[3], wg, smem); break;
+    case 4: syn_basis<10, P>(A, A.b[4], wg, smem); break;
+    case 5: syn_basis<12, P>(A, A.b[5], wg, smem); break;
+    case 6: syn_basis<14, P>(A, A.b[6], wg, smem); break;
+    default: syn_basis<16, P>(A, A.b[7], wg, smem); break;
+  }
+}
+
+static int syn_segp(int tk, int L) { return ((tk + kMaxTap / 2 - 1) * L + 63) / 64 * 64; }
+
+int launch_synthesis(const SynArgs &a, int nthreads, void *stream) {
+  const int nwg = a.wg_prefix[kBases];
+  if (nwg <= 0) return FHS_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int segp = syn_segp(a.tk, a.L);
+  const int P = 2 * 4 * 4 * segp * 4 <= 65536 ? 4 : 2;
+  const size_t lds = static_cast<size_t>(2 * 4 * P * segp) * sizeof(float);
+  if (P == 4)
+    hipLaunchKernelGGL(syn_kernel<4>, dim3(nwg), dim3(nthreads), lds, s, a);
+  else
+    hipLaunchKernelGGL(syn_kernel<2>, dim3(nwg), dim3(nthreads), lds, s, a);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(FHS_EHIP, std::string("synthesis launch: ") + hipGetErrorString(err));
+  return FHS_OK;
+}
+
+// ---------------------------------------------------------------- level 1
+
+namespace {
+
+// Bases [0, kFinalSplit) go in the first final-level pass, the rest in the second.
+constexpr int kFinalSplit = FHS_FINAL_SPLIT;
+
+// LDS floats of one staged band row of basis b.
+__device__ __forceinline__ int fin_segp(int tk, int b, int L) { return round_up((tk + b) * L, 64); }
+
+// The rings of bases b .. BEND-1 (basis b has 2(b+1) taps and b+1 rows per ring).
+// At output step s basis b needs coefficient row ks + s + b, so it starts b
+// steps before the first output.
+template <int b, int BEND, int P>
+struct RingSet {
+  Ring<2 * (b + 1)> r;
+  RingSet<b + 1, BEND, P> next;
+  __device__ __forceinline__ void zero() {
+    ring_zero(r);
+    next.zero();
+  }
+  // rows of steps s0 .. s0+P-1 of this basis into its region of the phase buffer
+  __device__ __forceinline__ void issue(const SynFinalArgs &A, int s0, int ks, int kx0, int L, float *lds) {
+    const int segp = fin_segp(A.tk, b, L);
+    issue_band_rows(A.b[b], ks + s0 + b, P, kx0, (A.tk + b) * L, segp, L, lds);
+    next.issue(A, s0, ks, kx0, L, lds + 4 * P * segp);
+  }
+  __device__ __forceinline__ void push(const SynFinalArgs &A, int s, int k, int off, int L, const float *lds) {
+    const int segp = fin_segp(A.tk, b, L);
+    if (s >= -b) ring_push<2 * (b + 1)>(lds + 4 * k * segp, segp, off, L, r);
+    next.push(A, s, k, off, L, lds + 4 * P * segp);
+  }
+  __device__ __forceinline__ void out(float acc[2][2]) {
+    ring_out<2 * (b + 1)>(r, acc);
+    next.out(acc);
+  }
+};
+
+template <int BEND, int P>
+struct RingSet<BEND, BEND, P> {
+  __device__ __forceinline__ void zero() {}
+  __device__ __forceinline__ void issue(const SynFinalArgs &, int, int, int, int, float *) {}
+  __device__ __forceinline__ void push(const SynFinalArgs &, int, int, int, int, const float *) {}
+  __device__ __forceinline__ void out(float[2][2]) {}
+};
+
+}  // namespace
+
+// Bases B0 .. B1-1 of level 1 summed into the image; FIRST also adds the Dirac
+// basis and applies beta, the second group accumulates onto the first.
+template <int B0, int B1, bool FIRST, int P>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FHS_FINAL_WPE)))
+syn_final_kernel(SynFinalArgs A) {
+  extern __shared__ float smem[];
+  const int L = A.L, Lcp = A.Lcp, C = A.C, Lc = A.Lc;
+  const int tid = threadIdx.x;
+  const int lane = tid % Lcp, grp = tid / Lcp, c = grp % C, kq = grp / C;
+  const bool lv = lane < Lc;
+  const int p = c * Lc + lane;
+  const int ch = c + lane * C;
+  const int strip = blockIdx.x % A.strips, yb = blockIdx.x / A.strips;
+  const int kx0 = strip * A.tk;
+  const int y0 = yb * A.ty;
+  const int y1 = min(y0 + A.ty, A.ny);
+  const int ks = y0 / 2;
+  const int nout = (y1 - 1) / 2 - ks + 1;
+  const int x = 2 * (kx0 + kq);
+  const int off = kq * L + p;
+  int half = 0;  // floats of one phase buffer
+  for (int b = B0; b < B1; ++b) half += 4 * P * fin_segp(A.tk, b, L);
+  RingSet<B0, B1, P> R;
+  R.zero();
+  const float scale = A.alpha * (1.0f / 3.0f);
+  const int sfirst = -(B1 - 1);
+  const int nsteps = nout - sfirst;
+  const int nph = (nsteps + P - 1) / P;
+
+  // values read at the outputs of step s: the Dirac coefficient and beta's
+  // previous image (first group) or the image of the first group (second)
+  auto pre = [&](int s, float v[2][2], float gv[2][2]) {
+    const int kp = ks + s;
+#pragma unroll
+    for (int py = 0; py < 2; ++py)
+#pragma unroll
+      for (int px = 0; px < 2; ++px) {
+        const int y = 2 * kp + py;
+        v[py][px] = 0.0f;
+        gv[py][px] = 0.0f;
+        if (s >= 0 && s < nout && lv && y < y1 && x + px < A.nx) {
+          const int64_t pix = static_cast<int64_t>(y) * A.nx + x + px;
+          if (FIRST) {
+            v[py][px] = A.dirac[pix * L + p];
+            if (A.beta != 0.0f) gv[py][px] = A.x[pix * L + ch];
+          } else {
+            v[py][px] = A.x[pix * L + ch];
+          }
+        }
+      }
+  };
+  float vq[P][2][2], gq[P][2][2];
+#pragma unroll
+  for (int k = 0; k < P; ++k) pre(sfirst + k, vq[k], gq[k]);
+  R.issue(A, sfirst, ks, kx0, L, smem);
+
+  for (int ph = 0; ph < nph; ++ph) {
+    wait_loads_and_sync();
+    if (ph + 1 < nph) R.issue(A, sfirst + (ph + 1) * P, ks, kx0, L, smem + ((ph + 1) & 1) * half);
+    const float *buf = smem + (ph & 1) * half;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int s = sfirst + ph * P + k;
+      if (s < nout) {
+        float vcur[2][2], gcur[2][2];
+#pragma unroll
+        for (int py = 0; py < 2; ++py)
+#pragma unroll
+          for (int px = 0; px < 2; ++px) {
+            vcur[py][px] = vq[k][py][px];
+            gcur[py][px] = gq[k][py][px];
+          }
+        pre(s + P, vq[k], gq[k]);
+        R.push(A, s, k, off, L, buf);
+        if (s >= 0) {
+          float acc[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
+          R.out(acc);
+          const int kp = ks + s;
+#pragma unroll
+          for (int py = 0; py < 2; ++py) {
+            const int y = 2 * kp + py;
+#pragma unroll
+            for (int px = 0; px < 2; ++px) {
+              if (lv && y < y1 && x + px < A.nx) {
+                float *dst = A.x + (static_cast<int64_t>(y) * A.nx + x + px) * L + ch;
+                if (FIRST) {
+                  const float v = scale * (acc[py][px] + vcur[py][px]);
+                  *dst = A.beta != 0.0f ? fmaf(A.beta, gcur[py][px], v) : v;
+                } else {
+                  *dst = fmaf(scale, acc[py][px], vcur[py][px]);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  drain_loads();
+}
+
+static int final_half_floats(int tk, int L, int b0, int b1, int P) {
+  int half = 0;
+  for (int b = b0; b < b1; ++b) half += 4 * P * (((tk + b) * L + 63) / 64 * 64);
+  return half;
+}
+
+template <int B0, int B1, bool FIRST>
+static void launch_final_group(const SynFinalArgs &a, int nthreads, hipStream_t s) {
+  const int nwg = a.strips * a.yblocks;
+  const int P = 2 * final_half_floats(a.tk, a.L, B0, B1, 2) * 4 <= 65536 ? 2 : 1;
+  const size_t lds = static_cast<size_t>(2 * final_half_floats(a.tk, a.L, B0, B1, P)) * sizeof(float);
+  if (P == 2)
+    hipLaunchKernelGGL((syn_final_kernel<B0, B1, FIRST, 2>), dim3(nwg), dim3(nthreads), lds, s, a);
+  else
+    hipLaunchKernelGGL((syn_final_kernel<B0, B1, FIRST, 1>), dim3(nwg), dim3(nthreads), lds, s, a);
+}
+
+// group 0: bases [0, kFinalSplit) + Dirac (applies beta); group 1: the rest.
+int launch_synthesis_final(const SynFinalArgs &a, int nthreads, int group, void *stream) {
+  if (a.strips * a.yblocks <= 0) return FHS_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (group == 0)
+    launch_final_group<0, kFinalSplit, true>(a, nthreads, s);
+  else
+    launch_final_group<kFinalSplit, kBases, false>(a, nthreads, s);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(FHS_EHIP, std::string("final synthesis launch: ") + hipGetErrorString(err));
+  return FHS_OK;
+}
+
+}  // namespace fhs
