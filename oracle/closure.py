@@ -1,0 +1,60 @@
+"""Rest of one PDFB iteration around the facet step (oracle).
+
+TEST INFRASTRUCTURE ONLY.
+
+The measurement operator is out of scope, so the data-fidelity block uses
+the identity as a stand-in (denoising: y = X_true + noise), with the paper's
+l2-ball constraint per channel and U = I, eta = 1:
+
+* data dual (Alg. 2, steps alg:step:dual_data1 / dual_data2 with Phi = I):
+      v <- (I - proj_{B(y, eps)})(v + Xcheck),
+  proj_{B(y, eps)}(z) = y + (z - y) / max(||z - y|| / eps, 1)   (Table 1);
+* aggregation (step alg:step:aggregate): A = G + v, G the facet part;
+* primal update (step alg:step:primal) and extrapolation:
+      X+ = max(0, X - tau A)  (projection onto the non-negative orthant, Table 1),
+      Xcheck = 2 X+ - X;
+* relative variation xi = ||X+ - X||_F / ||X||_F.
+
+eps_l^2 = sigma_l^2 (M_l + 2 sqrt(M_l)) with M_l = N measurements per channel
+(Sec. 2.2, noise statistics of the l2 ball).
+"""
+import numpy as np
+
+from . import step
+
+
+def l2_ball_radius(sigma, n):
+    return np.sqrt(sigma ** 2 * (n + 2.0 * np.sqrt(n)))
+
+
+def project_l2_ball(z, y, eps):
+    """Per-channel projection of z onto B(y, eps); arrays (ny, nx, L), eps (L,)."""
+    z = np.asarray(z, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    d = z - y
+    nrm = np.sqrt(np.sum(d * d, axis=(0, 1)))
+    return y + d / np.maximum(nrm / np.asarray(eps, dtype=np.float64), 1.0)
+
+
+def data_dual_update(v, xcheck, y, eps):
+    z = np.asarray(v, dtype=np.float64) + np.asarray(xcheck, dtype=np.float64)
+    return z - project_l2_ball(z, y, eps)
+
+
+def primal_update(x, grad, v, tau):
+    """Returns (X+, Xcheck, xi)."""
+    x = np.asarray(x, dtype=np.float64)
+    xn = np.maximum(0.0, x - tau * (np.asarray(grad, dtype=np.float64) + np.asarray(v, dtype=np.float64)))
+    nx = np.linalg.norm(x)
+    xi = np.linalg.norm(xn - x) / nx if nx > 0 else np.inf
+    return xn, 2.0 * xn - x, xi
+
+
+def pdfb_iteration(x, xcheck, P, W, v, y, eps, theta, theta_bar, mu, mu_bar, geom, C=1, tau=0.33, zeta=1.0,
+                   kappa=1.0):
+    """One iteration of Algorithm 2 with the identity data term.
+    Returns (x, xcheck, P, W, v, xi)."""
+    P, W, G = step.facet_prox_step(xcheck, P, W, theta, theta_bar, mu, mu_bar, zeta, kappa, geom, C=C)
+    v = data_dual_update(v, xcheck, y, eps)
+    x, xcheck, xi = primal_update(x, G, v, tau)
+    return x, xcheck, P, W, v, xi
