@@ -13,7 +13,6 @@ value = voxels / s (N * L per step), with a roofline entry for one kernel
 timed on a bounded sample as the CPU baseline.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -65,15 +64,6 @@ def step_bytes(plan, w):
     return 4 * (s["n_x"] + 2 * s["n_p"] + 2 * s["n_w"] + s["n_theta"] + s["n_x"])
 
 
-def source_hash():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2003_07358_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".cpp", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profiles(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
     taken on the current kernel sources; else None."""
@@ -81,6 +71,7 @@ def traffic_from_profiles(kernel, workload):
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
+    from paper_2003_07358_amd.profiling import source_hash
     if d.get("source_hash") != source_hash():
         return None
     return d.get("hbm_bytes_per_launch")
@@ -131,6 +122,9 @@ def main():
     ap.add_argument("--kernel", default="analysis_l1", help="kernel reported in the roofline entry")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of this many MiB (the reference "
+                         "dispatch that scales HBM counters read under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of the "
@@ -162,6 +156,16 @@ def main():
 
     def one_step():
         plan.facet_prox_step(x_d, p_d, w_d, th_d, tb_d, mu_d, mub_d, 1.0, 1.0, g_d)
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)          # one elementwise kernel: reads n * 4 B, writes n * 4 B
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy kernel: {n * 4} bytes read, {n * 4} bytes written")
+        del src, dst
 
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):

@@ -7,11 +7,11 @@
  * sub-cube c and spatial facet q, two dual variables and aggregates their
  * contributions into the primal gradient:
  *
- *   nuclear  (Alg. 2, step alg:step:dual_lr; Table 1 SVT):
+ *   nuclear  (Alg. 2, nuclear-norm dual update; Table 1 SVT):
  *     P_{c,q} <- (I - prox_{zeta^-1 mu_bar_{c,q} ||.||_{*,theta_bar_{c,q}}})(P_{c,q} + D_q S~_q Xcheck_c)
- *   l21      (Alg. 2, step alg:step:dual_sparsity; Table 1 row shrink):
+ *   l21      (Alg. 2, l21 dual update; Table 1 row shrink):
  *     W_{c,q} <- (I - prox_{kappa^-1 mu_c ||.||_{2,1,theta_{c,q}}})(W_{c,q} + Psi_q^dagger S_q Xcheck_c)
- *   gather   (Alg. 2, step alg:step:aggregate, facet part):
+ *   gather   (Alg. 2, aggregation, facet part):
  *     G_c = sum_q zeta S~_q^T D_q P_{c,q} + kappa S_q^T Psi_q W_{c,q}
  *
  * Psi^dagger is the SARA dictionary (Sec. 2.3.1): Daubechies db1..db8 at
@@ -142,12 +142,12 @@ int fhs_plan_set_workspace(fhs_plan *plan, void *dev_ptr, int64_t bytes);
  * in natural channel order, w [I][L] in channel positions. */
 int fhs_sara_analysis(const fhs_plan *plan, const float *x, float *w, void *stream);
 
-/* x = beta x + alpha Psi w, Psi the adjoint of Psi^dagger (Alg. 2, step
- * alg:step:end_facet-l21 summed over facets). */
+/* x = beta x + alpha Psi w, Psi the adjoint of Psi^dagger (Alg. 2, facet synthesis
+ * summed over facets). */
 int fhs_sara_synthesis(const fhs_plan *plan, const float *w, float *x, float alpha, float beta,
                        void *stream);
 
-/* l21 dual update of every facet (Alg. 2, step alg:step:dual_sparsity) and its
+/* l21 dual update of every facet (Alg. 2, l21 dual update) and its
  * gather: for every coefficient row i and sub-cube c,
  *   u = W_i + [Psi^dagger Xcheck_c]_i,  W_i <- u min(1, (mu_c / kappa) theta_{c,i} / ||u||_2)
  *   (W_i <- 0 when u = 0),
@@ -157,32 +157,84 @@ int fhs_l21_dual_update(const fhs_plan *plan, const float *xcheck, float *w_inou
                         const float *theta, const double *mu, double kappa, float *grad,
                         float beta, void *stream);
 
-/* Weighted nuclear-norm dual update of every facet (Alg. 2, step
- * alg:step:dual_lr) and its gather: Z = P_f + D_q S~_q Xcheck_c (N~_q x L_c),
+/* Weighted nuclear-norm dual update of every facet (Alg. 2) and its gather:
+ * Z = P_f + D_q S~_q Xcheck_c (N~_q x L_c),
  * thresholds t_j = (mu_bar_f / zeta) theta_bar_{f,j} paired with the singular
  * values s_1 >= s_2 >= ..., and
  *   P_f <- Z - prox(Z) = U Diag(min(s_j, t_j)) V^T = Z V Diag(min(1, t_j / s_j)) V^T,
- * then grad = beta grad + zeta sum_f S~_q^T D_q P_f (step
- * alg:step:end_facet-nuclear and the aggregation).  P is updated in place. */
+ * then grad = beta grad + zeta sum_f S~_q^T D_q P_f (facet
+ * back-projection and aggregation).  P is updated in place. */
 int fhs_nuclear_dual_update(const fhs_plan *plan, const float *xcheck, float *p_inout,
                             const double *theta_bar, const double *mu_bar, double zeta,
                             float *grad, float beta, void *stream);
 
 /* Both dual updates and the full facet part of the aggregation (Alg. 2,
- * facet loop and step alg:step:aggregate):
+ * facet loop and aggregation):
  *   grad = zeta sum_f S~_q^T D_q P_f + kappa Psi W   (grad overwritten). */
 int fhs_facet_prox_step(const fhs_plan *plan, const float *xcheck, float *p_inout,
                         float *w_inout, const float *theta, const double *theta_bar,
                         const double *mu, const double *mu_bar, double zeta, double kappa,
                         float *grad, void *stream);
 
-/* Reweighting weights from the previous iterate X^(t) (Alg. 1, steps
- * alg:step:weights_nuclear and alg:step:weights_l21):
+/* Reweighting weights from the previous iterate X^(t) (Alg. 1,
+ * weight updates):
  *   theta_bar_{f,j} = upsilon_bar_f / (s_j(D_q S~_q X_c) + upsilon_bar_f)  (eq. facet_hypersara_rank)
  *   theta_{c,i}     = upsilon_c / (||[Psi^dagger X_c]_i||_2 + upsilon_c)    (eq. facet_hypersara_sparsity)
  * upsilon [C] and upsilon_bar [C*Q] are float64 device arrays. */
 int fhs_reweight(const fhs_plan *plan, const float *x, const double *upsilon,
                  const double *upsilon_bar, float *theta, double *theta_bar, void *stream);
+
+/* ---------------------------------------------------------------- PDFB iteration */
+
+/* The rest of an iteration of Algorithm 2 around the facet step, with the
+ * identity as measurement operator (a denoising stand-in for the
+ * data-fidelity block, whose operator is outside this library), U = I and
+ * eta = 1:
+ *   v      <- (I - proj_{B(y_l, eps_l)})(v + xcheck)   per channel l (Table 1)
+ *   x+      = max(0, x - tau (grad + v))               (primal update, Table 1)
+ *   xcheck <- 2 x+ - x,   x <- x+                      (extrapolation)
+ *   *xi     = ||x+ - x||_F / ||x||_F  (+inf if x = 0)  (relative variation)
+ * x, xcheck, v, y, grad: float32 [ny][nx][L] (natural channel order); eps:
+ * float64 [L]; xi: one float64.  All device pointers; x, xcheck, v are
+ * updated in place and must not alias y or grad.  The channel norms and xi
+ * are accumulated in float64 in a fixed order (bitwise reproducible).  Uses
+ * the plan's workspace. */
+int fhs_pdfb_closure(const fhs_plan *plan, float *x, float *xcheck, float *v, const float *y,
+                     const double *eps, const float *grad, double tau, double *xi, void *stream);
+
+/* Everything one PDFB iteration touches (device pointers, caller-owned). */
+typedef struct {
+  float *x;                 /* X [ny][nx][L]                                    */
+  float *xcheck;            /* Xcheck [ny][nx][L]                               */
+  float *p;                 /* nuclear duals, packed (see P above)              */
+  float *w;                 /* l21 duals [I][L]                                 */
+  float *v;                 /* data-fidelity dual [ny][nx][L]                   */
+  const float *y;           /* data [ny][nx][L]                                 */
+  const double *eps;        /* l2-ball radius per channel [L]                   */
+  const float *theta;       /* [C][I]                                           */
+  const double *theta_bar;  /* [C*Q][L_c]                                       */
+  const double *mu;         /* [C]                                              */
+  const double *mu_bar;     /* [C*Q]                                            */
+  float *grad;              /* facet gradient, overwritten [ny][nx][L]          */
+  double *xi;               /* relative variation, one float64 per iteration    */
+  double zeta, kappa, tau;  /* dual and primal step sizes (tau > 0)            */
+} fhs_pdfb_state;
+
+/* One iteration: fhs_facet_prox_step on xcheck (into grad), then
+ * fhs_pdfb_closure, writing xi[iter]. */
+int fhs_pdfb_iteration(const fhs_plan *plan, const fhs_pdfb_state *state, int32_t iter, void *stream);
+
+/* A HIP graph of n_iter consecutive iterations (xi[0 .. n_iter-1]), captured
+ * on a stream of the library's own and instantiated; it bakes in the
+ * pointers of *state and the plan's workspace, so those must outlive it and
+ * launches that share them must not overlap.  Fails with FHS_EINVAL while
+ * kernel profiling is enabled.  The graph holds no device allocation. */
+typedef struct fhs_graph fhs_graph;
+int fhs_pdfb_graph_create(const fhs_plan *plan, const fhs_pdfb_state *state, int32_t n_iter,
+                          fhs_graph **out);
+/* Launches the whole graph on `stream` (asynchronous). */
+int fhs_graph_launch(const fhs_graph *graph, void *stream);
+void fhs_graph_destroy(fhs_graph *graph);
 
 /* ---------------------------------------------------------------- diagnostics */
 
@@ -196,7 +248,8 @@ int fhs_reweight(const fhs_plan *plan, const float *x, const double *upsilon,
 #define FHS_K_NUC_EIG 6
 #define FHS_K_NUC_RECON 7
 #define FHS_K_NUC_GATHER 8
-#define FHS_K_COUNT 9
+#define FHS_K_CLOSURE 9       /* data dual + primal update (the four closure kernels)     */
+#define FHS_K_COUNT 10
 
 /* Times every launch of kernel `kernel_id` (or none if -1) with HIP events
  * recorded on the launch stream around it.  Creates up to `max_launches`

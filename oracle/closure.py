@@ -6,11 +6,11 @@ The measurement operator is out of scope, so the data-fidelity block uses
 the identity as a stand-in (denoising: y = X_true + noise), with the paper's
 l2-ball constraint per channel and U = I, eta = 1:
 
-* data dual (Alg. 2, steps alg:step:dual_data1 / dual_data2 with Phi = I):
+* data dual (Alg. 2, data-fidelity dual update with Phi = I):
       v <- (I - proj_{B(y, eps)})(v + Xcheck),
   proj_{B(y, eps)}(z) = y + (z - y) / max(||z - y|| / eps, 1)   (Table 1);
-* aggregation (step alg:step:aggregate): A = G + v, G the facet part;
-* primal update (step alg:step:primal) and extrapolation:
+* aggregation (aggregation): A = G + v, G the facet part;
+* primal update (primal update) and extrapolation:
       X+ = max(0, X - tau A)  (projection onto the non-negative orthant, Table 1),
       Xcheck = 2 X+ - X;
 * relative variation xi = ||X+ - X||_F / ||X||_F.

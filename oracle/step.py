@@ -4,17 +4,17 @@ TEST INFRASTRUCTURE ONLY.
 
 For every spectral sub-cube c and spatial facet q (Algorithm 2, facet loop):
 
-  nuclear dual update (step alg:step:dual_lr, prox of Table 1):
+  nuclear dual update (prox of Table 1):
       P_{c,q} <- (I - prox_{zeta^-1 mu_bar_{c,q} ||.||_{*,theta_bar_{c,q}}})(P_{c,q} + D_q S~_q X_c)
       with thresholds t_j = (mu_bar_{c,q} / zeta) theta_bar_{c,q,j};
-      then P~_{c,q} = D_q P_{c,q} (step alg:step:end_facet-nuclear; the printed
+      then P~_{c,q} = D_q P_{c,q} (facet back-projection; the printed
       "D_q^dagger P_c" is read as D_q P_{c,q}, D_q being real diagonal).
 
-  l21 dual update (step alg:step:dual_sparsity):
+  l21 dual update (row shrink of Table 1):
       W_{c,q} <- (I - prox_{kappa^-1 mu_c ||.||_{2,1,theta_{c,q}}})(W_{c,q} + Psi_q^dagger S_q X_c)
-      then W~_{c,q} = Psi_q W_{c,q} (step alg:step:end_facet-l21).
+      then W~_{c,q} = Psi_q W_{c,q} (facet synthesis).
 
-  facet part of the aggregation (step alg:step:aggregate):
+  facet part of the aggregation:
       A_c = sum_q zeta S~_q^T P~_{c,q} + kappa S_q^T W~_{c,q}.
 
 The faceted wavelet transform is exactly the global one (Sec. 2.4.2), so the

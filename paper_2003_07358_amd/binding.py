@@ -29,6 +29,12 @@ class _Sizes(ctypes.Structure):
                  "workspace_bytes")]
 
 
+class _PdfbState(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("x", "xcheck", "p", "w", "v", "y", "eps", "theta", "theta_bar", "mu", "mu_bar", "grad", "xi")] + \
+               [(n, ctypes.c_double) for n in ("zeta", "kappa", "tau")]
+
+
 SYMBOLS = {
     "fhs_version": (ctypes.c_int, []),
     "fhs_last_error": (ctypes.c_char_p, []),
@@ -57,6 +63,15 @@ SYMBOLS = {
                                            ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "fhs_reweight": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_pdfb_closure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_pdfb_iteration": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_PdfbState), ctypes.c_int32,
+                                          ctypes.c_void_p]),
+    "fhs_pdfb_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_PdfbState), ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_void_p)]),
+    "fhs_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_graph_destroy": (None, [ctypes.c_void_p]),
     "fhs_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "fhs_plan_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_int64)]),
@@ -65,7 +80,7 @@ SYMBOLS = {
 # kernel identifiers of fhs_plan_profile (include/fhs.h)
 KERNELS = {
     "analysis_l1": 0, "analysis": 1, "synthesis": 2, "synth_final_a": 3, "synth_final_b": 4,
-    "nuc_gram": 5, "nuc_eig": 6, "nuc_recon": 7, "nuc_gather": 8,
+    "nuc_gram": 5, "nuc_eig": 6, "nuc_recon": 7, "nuc_gather": 8, "closure": 9,
 }
 
 
@@ -236,6 +251,56 @@ class Plan:
             self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"), float(zeta), float(kappa),
             self._t(grad, s["n_x"], torch.float32, "grad"), _stream(xcheck)))
 
+    # ------------------------------------------------------------ PDFB iterations
+    def pdfb_closure(self, x, xcheck, v, y, eps, grad, tau, xi):
+        """Data-fidelity dual (identity operator), primal update, extrapolation;
+        xi: a one-element float64 device tensor receiving the relative variation."""
+        import torch
+        self._need_ws()
+        n = self.sizes["n_x"]
+        _check(self._lib.fhs_pdfb_closure(
+            self._p, self._t(x, n, torch.float32, "x"), self._t(xcheck, n, torch.float32, "xcheck"),
+            self._t(v, n, torch.float32, "v"), self._t(y, n, torch.float32, "y"),
+            self._t(eps, self.L, torch.float64, "eps"), self._t(grad, n, torch.float32, "grad"), float(tau),
+            self._t(xi, 1, torch.float64, "xi"), _stream(x)))
+
+    def pdfb_state(self, x, xcheck, p, w, v, y, eps, theta, theta_bar, mu, mu_bar, grad, xi, zeta=1.0,
+                   kappa=1.0, tau=0.33):
+        """Checked state block for pdfb_iteration / pdfb_graph (xi: float64, one
+        entry per iteration).  The tensors must stay alive while it is used."""
+        import torch
+        s = self.sizes
+        n = s["n_x"]
+        if not (isinstance(xi, torch.Tensor) and xi.is_cuda and xi.dtype == torch.float64 and xi.is_contiguous()):
+            raise FhsError("xi: expected a contiguous float64 device tensor")
+        st = _PdfbState(
+            self._t(x, n, torch.float32, "x"), self._t(xcheck, n, torch.float32, "xcheck"),
+            self._t(p, s["n_p"], torch.float32, "p"), self._t(w, s["n_w"], torch.float32, "w"),
+            self._t(v, n, torch.float32, "v"), self._t(y, n, torch.float32, "y"),
+            self._t(eps, self.L, torch.float64, "eps"), self._t(theta, s["n_theta"], torch.float32, "theta"),
+            self._t(theta_bar, s["n_theta_bar"], torch.float64, "theta_bar"),
+            self._t(mu, self.C, torch.float64, "mu"), self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"),
+            self._t(grad, n, torch.float32, "grad"), ctypes.c_void_p(xi.data_ptr()),
+            float(zeta), float(kappa), float(tau))
+        st.n_xi = xi.numel()
+        st.device = x.device
+        return st
+
+    def pdfb_iteration(self, state, it=0):
+        self._need_ws()
+        if not 0 <= it < state.n_xi:
+            raise FhsError("iteration index outside xi")
+        import torch
+        _check(self._lib.fhs_pdfb_iteration(self._p, ctypes.byref(state), int(it),
+                                            ctypes.c_void_p(torch.cuda.current_stream(state.device).cuda_stream)))
+
+    def pdfb_graph(self, state, n_iter):
+        """HIP graph of n_iter iterations (xi[0 .. n_iter-1])."""
+        self._need_ws()
+        if not 1 <= n_iter <= state.n_xi:
+            raise FhsError("n_iter must be in [1, len(xi)]")
+        return Graph(self, state, n_iter)
+
     # ------------------------------------------------------------ diagnostics
     def profile(self, kernel, max_launches=4096):
         """Time every launch of `kernel` (name from KERNELS, or None to stop)."""
@@ -258,3 +323,29 @@ class Plan:
             self._t(upsilon_bar, s["n_facets"], torch.float64, "upsilon_bar"),
             self._t(theta, s["n_theta"], torch.float32, "theta"),
             self._t(theta_bar, s["n_theta_bar"], torch.float64, "theta_bar"), _stream(x)))
+
+
+class Graph:
+    """A captured sequence of PDFB iterations (fhs_pdfb_graph_create)."""
+
+    def __init__(self, plan, state, n_iter):
+        self._lib = plan._lib
+        self._plan, self._state = plan, state   # keep both alive with the graph
+        handle = ctypes.c_void_p()
+        _check(self._lib.fhs_pdfb_graph_create(plan._p, ctypes.byref(state), int(n_iter), ctypes.byref(handle)))
+        self._g = handle
+        self.n_iter = n_iter
+
+    def launch(self):
+        import torch
+        _check(self._lib.fhs_graph_launch(self._g, ctypes.c_void_p(
+            torch.cuda.current_stream(self._state.device).cuda_stream)))
+
+    def close(self):
+        g = getattr(self, "_g", None)
+        if g is not None and g.value:
+            self._lib.fhs_graph_destroy(g)
+            self._g = None
+
+    def __del__(self):
+        self.close()

@@ -1,5 +1,5 @@
 // SARA analysis with the fused l21 dual update, for gfx950 (Sec. 2.3.1; Alg. 2
-// step alg:step:dual_sparsity; row shrink of Table 1).
+// l21 dual update; row shrink of Table 1).
 //
 // Transform: zero-extended expansive separable DWT, causal index convention
 // a[k] = sum_m h[m] x[2k+1-m], k < floor((n+L-1)/2), along columns and rows,

@@ -110,6 +110,19 @@ struct GatherArgs {
   float beta;
 };
 
+// Data-fidelity dual (identity operator), primal update and relative variation.
+struct ClosureArgs {
+  float *x, *xcheck, *v;
+  const float *y, *grad;
+  const double *eps;   // [L] l2-ball radii
+  double *part;        // [nblocks][max(L, 2)] block partial sums (workspace)
+  double *factor;      // [L] dual scale factors (workspace)
+  double *xi;          // one double: relative variation of this iteration
+  double tau;
+  int64_t npix, ppb;   // pixels, pixels per block
+  int L, nblocks;
+};
+
 // ---------------------------------------------------------------- launchers
 int launch_analysis(const AnaArgs &a, int nthreads, bool first, void *stream);
 int launch_synthesis(const SynArgs &a, int nthreads, void *stream);
@@ -118,6 +131,7 @@ int launch_nuc_gram(const NucArgs &a, int nfacets, void *stream);
 int launch_nuc_eig(const NucArgs &a, int nfacets, void *stream);
 int launch_nuc_recon(const NucArgs &a, int nfacets, int rowblocks, void *stream);
 int launch_nuc_gather(const GatherArgs &a, void *stream);
+int launch_closure(const ClosureArgs &a, void *stream);
 
 }  // namespace fhs
 
@@ -143,7 +157,9 @@ struct fhs_plan {
   int ntap[fhs::kBases];
   // workspace layout (bytes)
   int64_t ws_ll[fhs::kBases][fhs::kMaxLevels];
-  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_bytes = 0;
+  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_red = 0, ws_factor = 0, ws_bytes = 0;
+  int64_t red_ppb = 0;                     // closure: pixels per block
+  int red_blocks = 0;                      // closure: blocks
   int gram_chunks = 0, gram_chunk_rows = 0, max_rows = 0;
   void *ws = nullptr;
   int64_t ws_given = 0;

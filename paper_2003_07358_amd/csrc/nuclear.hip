@@ -1,5 +1,5 @@
-// Weighted nuclear-norm dual update for gfx950 (Alg. 2, steps
-// alg:step:dual_lr and alg:step:end_facet-nuclear; SVT of Table 1).
+// Weighted nuclear-norm dual update for gfx950 (Alg. 2, the
+// nuclear-norm dual update and facet back-projection; SVT of Table 1).
 //
 // For facet f (sub-cube c, spatial facet q) with Z = P_f + D_q S~_q Xcheck_c
 // (N~_q x L_c):

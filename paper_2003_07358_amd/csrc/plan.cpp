@@ -6,6 +6,7 @@
 // window D_q is evaluated on the fly by the kernels from these bounds.
 // Wavelet bands: zero-extended expansive transform, K = floor((n + L - 1) / 2)
 // coefficients per band and level for an input of n samples and L taps.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -183,6 +184,18 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   ws = align256(ws + nf * p->lc16 * p->lc16 * 8);
   p->ws_sig = ws;
   ws = align256(ws + nf * p->Lc * 8);
+  // closure sums: about 2048 blocks of whole pixel groups
+  {
+    const int64_t npix = static_cast<int64_t>(c.ny) * c.nx;
+    const int64_t G = std::max(1, 256 / p->L);
+    const int64_t per = (npix + G * 2048 - 1) / (G * 2048);
+    p->red_ppb = G * std::max<int64_t>(1, per);
+    p->red_blocks = static_cast<int>((npix + p->red_ppb - 1) / p->red_ppb);
+  }
+  p->ws_red = ws;
+  ws = align256(ws + static_cast<int64_t>(p->red_blocks) * std::max(p->L, 2) * 8);
+  p->ws_factor = ws;
+  ws = align256(ws + static_cast<int64_t>(p->L) * 8);
   p->ws_bytes = ws;
   *out = p;
   return FHS_OK;

@@ -1,6 +1,6 @@
 // SARA synthesis Psi w for gfx950: the exact adjoint of the analysis (Sec.
-// 2.3.1; Alg. 2 step alg:step:end_facet-l21 summed over facets and the kappa
-// term of step alg:step:aggregate).
+// 2.3.1; Alg. 2 facet synthesis summed over facets and the kappa
+// term of aggregation).
 //
 // One level of the adjoint: an output sample x = 2k + px receives
 // sum_{i < L/2} f[2i + 1 - px] c[k + i], so a thread owning coefficient column k

@@ -1,0 +1,158 @@
+"""Summaries of rocprofv3 output for the library's kernels.
+
+    python -m paper_2003_07358_amd.profiling stats DIR --out FILE --command CMD
+        per-kernel launch count and durations from a --kernel-trace run
+    python -m paper_2003_07358_amd.profiling traffic --fetch DIR --write DIR
+            --kernel REGEX --calib REGEX --calib-bytes B --name NAME --out FILE --command CMD
+        HBM bytes per launch of the kernels matching REGEX from two --pmc runs
+        (FETCH_SIZE, WRITE_SIZE), each scaled by the reading of a reference
+        copy kernel that moves a known number of bytes
+
+DIR is the rocprofv3 output directory (its SQLite results database).  The
+source hash written with the traffic summary names the kernel sources the
+counters were taken on; a summary taken on other sources is stale.
+"""
+import argparse
+import collections
+import glob
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def _code_only(text):
+    """Source text without comments and blank lines (edits to comments do not
+    change the kernels)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(CSRC, f)) as fh:
+                h.update(f.encode())
+                h.update(_code_only(fh.read()).encode())
+    return h.hexdigest()[:16]
+
+
+def _db(d):
+    found = sorted(glob.glob(os.path.join(d, "**", "*.db"), recursive=True))
+    if not found:
+        raise FileNotFoundError(f"no rocprofv3 database under {d}")
+    return sqlite3.connect(found[0])
+
+
+def short_name(name):
+    """Kernel name without the argument list (template arguments kept)."""
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def kernel_stats(d):
+    c = _db(d)
+    rows = c.execute("select name, duration from kernels").fetchall()
+    agg = collections.defaultdict(list)
+    for name, dur in rows:
+        agg[short_name(name)].append(dur)
+    total = sum(sum(v) for v in agg.values())
+    out = []
+    for name, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        out.append({"kernel": name, "calls": len(v), "avg_us": sum(v) / len(v) / 1e3, "min_us": min(v) / 1e3,
+                    "max_us": max(v) / 1e3, "total_ms": sum(v) / 1e6, "pct": 100.0 * sum(v) / total})
+    return out
+
+
+def counter_per_dispatch(d, counter):
+    """{kernel short name: [value per dispatch]} for one counter."""
+    c = _db(d)
+    rows = c.execute("select kernel_name, dispatch_id, sum(value) from counters_collection where counter_name = ? "
+                     "group by dispatch_id", (counter,)).fetchall()
+    agg = collections.defaultdict(list)
+    for name, _, v in rows:
+        agg[short_name(name)].append(v)
+    return agg
+
+
+def _matching(agg, pattern):
+    rx = re.compile(pattern)
+    vals = [v for k, vs in agg.items() if rx.search(k) for v in vs]
+    if not vals:
+        raise ValueError(f"no dispatch matches {pattern!r}; kernels: {sorted(agg)}")
+    return vals
+
+
+def cmd_stats(a):
+    st = kernel_stats(a.dir)
+    lines = [f"# rocprofv3 kernel trace: {a.title or a.dir}", "", f"command: {a.command}", "",
+             f"{'kernel':<64} {'calls':>6} {'avg us':>10} {'min us':>10} {'max us':>10} {'total ms':>10} {'%':>6}"]
+    for r in st:
+        lines.append(f"{r['kernel'][:64]:<64} {r['calls']:>6} {r['avg_us']:>10.1f} {r['min_us']:>10.1f} "
+                     f"{r['max_us']:>10.1f} {r['total_ms']:>10.3f} {r['pct']:>6.1f}")
+    text = "\n".join(lines) + "\n"
+    with open(a.out, "w") as fh:
+        fh.write(text)
+    sys.stdout.write(text)
+
+
+def cmd_traffic(a):
+    res = {"name": a.name, "source_hash": source_hash(), "command": a.command, "kernel_regex": a.kernel,
+           "calib_regex": a.calib, "calib_bytes": a.calib_bytes}
+    total = 0.0
+    for key, d, counter in (("fetch", a.fetch, "FETCH_SIZE"), ("write", a.write, "WRITE_SIZE")):
+        agg = counter_per_dispatch(d, counter)
+        kern = _matching(agg, a.kernel)
+        cal = _matching(agg, a.calib)
+        kib = sum(kern) / len(kern)
+        cal_kib = max(cal)
+        scale = a.calib_bytes / (cal_kib * 1024.0)
+        res[f"{key}_kib_per_launch"] = kib
+        res[f"{key}_launches"] = len(kern)
+        res[f"{key}_calib_kib"] = cal_kib
+        res[f"{key}_scale"] = scale
+        res[f"{key}_bytes_per_launch"] = kib * 1024.0 * scale
+        total += kib * 1024.0 * scale
+    res["hbm_bytes_per_launch"] = total
+    with open(a.out, "w") as fh:
+        json.dump(res, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(res, indent=1))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--out", required=True)
+    s.add_argument("--command", default="")
+    s.add_argument("--title", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--calib", required=True)
+    t.add_argument("--calib-bytes", type=float, required=True)
+    t.add_argument("--name", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--command", default="")
+    a = ap.parse_args(argv)
+    (cmd_stats if a.cmd == "stats" else cmd_traffic)(a)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,3 +108,11 @@ def workload_cube(w: Workload, variant="plain"):
         return Xa
     Xb = blob_cube(w.ny, w.nx, w.L, w.blobs, seed + 1000)
     return (2.0 * Xa.astype(np.float64) - Xb).astype(np.float32)
+
+
+def noisy_data(X, frac, seed):
+    """Data of the denoising stand-in: y = X + sigma n, n ~ N(0, 1) i.i.d.,
+    sigma = frac max|X|.  Returns (y float32, sigma)."""
+    sigma = frac * float(np.max(np.abs(X)))
+    n = rng(seed).standard_normal(X.shape)
+    return (X.astype(np.float64) + sigma * n).astype(np.float32), sigma

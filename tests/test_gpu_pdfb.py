@@ -1,0 +1,152 @@
+"""GPU parity of the PDFB iteration (facet step + data-fidelity dual with the
+identity operator + primal update + extrapolation) against the FP64 oracle,
+and of its HIP-graph capture against eager launches.
+
+Bars: one closure call matches the oracle to 1e-6 (float64 arithmetic,
+float32 storage); after k iterations every state array is within k * 1e-5
+relative L2 (each step within 1e-5, carried through a non-expansive
+iteration) -- the data dual v relative to the norm of the step's input
+v + xcheck - y, since (I - proj) is 1-Lipschitz but v can be tiny next to
+its input; the relative variation within 2k * 1e-5 absolute.  A graph replay
+equals the same iterations launched eagerly bit for bit.
+"""
+import numpy as np
+import pytest
+
+import synth
+from fhs_cases import Problem, log, rel_l2
+from oracle import closure
+
+torch = pytest.importorskip("torch")
+fhs = pytest.importorskip("paper_2003_07358_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CLOSURE_CASES = {
+    "ragged_101x77x6": (101, 77, 6),
+    "cfg1_256x256x20": (256, 256, 20),
+    "l100_64x48x100": (64, 48, 100),
+    "l1_33x17x1": (33, 17, 1),
+    "l256_9x5x256": (9, 5, 256),
+}
+
+
+@pytest.mark.parametrize("name", list(CLOSURE_CASES))
+def test_closure_parity(name):
+    ny, nx, L = CLOSURE_CASES[name]
+    log(f"[case] closure {name}")
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0, 1, (ny, nx, L)).astype(np.float32)
+    xc = (x + 0.1 * rng.standard_normal(x.shape)).astype(np.float32)
+    v = (0.05 * rng.standard_normal(x.shape)).astype(np.float32)
+    y = rng.uniform(0, 1, (ny, nx, L)).astype(np.float32)
+    g = (0.3 * rng.standard_normal(x.shape)).astype(np.float32)
+    # radii: half the channels with v + xcheck inside the ball, half outside
+    r = np.linalg.norm((v.astype(np.float64) + xc - y), axis=(0, 1))
+    eps = np.where(np.arange(L) % 2 == 0, 0.5 * r, 2.0 * r)
+    C = next(c for c in range(1, L + 1) if L % c == 0 and L // c <= 64)
+    plan = fhs.Plan(ny, nx, L, n_sub=C, levels=1 if min(ny, nx) < 16 else 4).attach_workspace()
+    xt, xct, vt = dev(x), dev(xc), dev(v)
+    xi = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plan.pdfb_closure(xt, xct, vt, dev(y), dev(eps), dev(g), 0.33, xi)
+    vr = closure.data_dual_update(v, xc, y, eps)
+    xr, xcr, xir = closure.primal_update(x, g, vr, 0.33)
+    for nm, got, ref in (("v", host(vt), vr), ("x", host(xt), xr), ("xcheck", host(xct), xcr)):
+        e = rel_l2(got, ref)
+        log(f"    {nm}: rel_l2={e:.3e}")
+        assert e <= 1e-6, (nm, e)
+    xig = float(host(xi)[0])
+    log(f"    xi gpu={xig:.12e} oracle={xir:.12e}")
+    assert abs(xig - xir) <= 1e-12 * xir + 1e-15
+
+
+def pdfb_problem(ny, nx, L, qy, qx, C, o, levels=4, seed=0, blobs=12, frac=0.05):
+    pb = Problem(ny, nx, L, qy, qx, C, o, o, levels, seed=seed, blobs=blobs)
+    y, sig = synth.noisy_data(pb.X, frac, synth.BASE_SEED + 77 + seed)
+    eps = np.full(L, closure.l2_ball_radius(sig, ny * nx))
+    x0 = np.maximum(y, 0.0).astype(np.float32)
+    return pb, y, eps, x0
+
+
+def gpu_state(plan, pb, y, eps, x0, n_xi):
+    t = dict(x=dev(x0), xcheck=dev(x0), p=dev(pb.P_flat()), w=dev(pb.W_flat()),
+             v=torch.zeros(x0.size, dtype=torch.float32, device="cuda"), y=dev(y), eps=dev(eps),
+             theta=dev(pb.theta_flat()), theta_bar=dev(pb.theta_bar_flat()), mu=dev(pb.mu),
+             mu_bar=dev(pb.mu_bar_flat()), grad=torch.empty(x0.size, dtype=torch.float32, device="cuda"),
+             xi=torch.zeros(n_xi, dtype=torch.float64, device="cuda"))
+    return t, plan.pdfb_state(**t)
+
+
+PDFB_CASES = {
+    "q2x2_c2_64x64x12": dict(ny=64, nx=64, L=12, qy=2, qx=2, C=2, o=8),
+    "q3x2_c1_90x70x8": dict(ny=90, nx=70, L=8, qy=3, qx=2, C=1, o=6),
+}
+
+
+@pytest.mark.parametrize("name", list(PDFB_CASES))
+def test_pdfb_iterations_parity(name):
+    log(f"[case] pdfb {name}")
+    pb, y, eps, x0 = pdfb_problem(**PDFB_CASES[name])
+    plan = fhs.Plan(*pb.cfg).attach_workspace()
+    K = 5
+    t, st = gpu_state(plan, pb, y, eps, x0, K)
+    x, xc = x0.astype(np.float64), x0.astype(np.float64)
+    P, W, v = pb.P, pb.W, np.zeros(x0.shape)
+    for k in range(1, K + 1):
+        plan.pdfb_iteration(st, k - 1)
+        z_norm = np.linalg.norm(v + xc - y)   # input of the data-dual step
+        x, xc, P, W, v, xi = closure.pdfb_iteration(x, xc, P, W, v, y, eps, pb.theta, pb.theta_bar, pb.mu,
+                                                    pb.mu_bar, pb.geom, C=pb.C)
+        got = {n: host(t[n]) for n in ("x", "xcheck", "v", "p", "w")}
+        ref = {"x": x, "xcheck": xc, "v": v,
+               "p": np.concatenate([q.reshape(-1) for row in P for q in row]),
+               "w": np.concatenate(W, axis=1)}
+        for n in got:
+            if n == "v":
+                # v = (I - proj)(z) is 1-Lipschitz in z but can be tiny next to
+                # it (z just outside the ball): measure its error on z's scale
+                e = np.linalg.norm(got[n].reshape(-1) - ref[n].reshape(-1)) / z_norm
+            else:
+                e = rel_l2(got[n].reshape(-1), ref[n].reshape(-1))
+            log(f"    it {k} {n}: rel err={e:.3e}")
+            assert e <= k * 1e-5, (k, n, e)
+        xig = float(host(t["xi"])[k - 1])
+        log(f"    it {k} xi gpu={xig:.6e} oracle={xi:.6e}")
+        assert abs(xig - xi) <= 2 * k * 1e-5
+
+
+def test_pdfb_graph_replays_match_eager():
+    log("[case] graph vs eager, q2x2_c2_64x64x12, 6 iterations, 3 replays")
+    pb, y, eps, x0 = pdfb_problem(**PDFB_CASES["q2x2_c2_64x64x12"])
+    plan = fhs.Plan(*pb.cfg).attach_workspace()
+    n = 6
+    te, ste = gpu_state(plan, pb, y, eps, x0, n)
+    for i in range(n):
+        plan.pdfb_iteration(ste, i)
+    eager = {k: host(v).copy() for k, v in te.items()}
+    tg, stg = gpu_state(plan, pb, y, eps, x0, n)
+    init = {k: v.clone() for k, v in tg.items()}
+    graph = plan.pdfb_graph(stg, n)
+    for rep in range(3):
+        for k in tg:
+            tg[k].copy_(init[k])
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        for k in ("x", "xcheck", "v", "p", "w", "grad", "xi"):
+            assert np.array_equal(host(tg[k]), eager[k]), (rep, k)
+        # unrelated eager work between replays
+        (tg["grad"] * 2.0).sum().item()
+        log(f"    replay {rep}: identical")
+    graph.close()
+    assert np.isfinite(eager["xi"]).all() and (eager["xi"] > 0).all()
