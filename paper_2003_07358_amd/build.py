@@ -46,35 +46,40 @@ def gen_filters():
     return hdr
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _compile(src, build_dir=BUILD, defines=()):
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    flags = [*COMMON, *(f"-D{d}" for d in defines)]
     if src.endswith(".hip"):
-        cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, "-c", src, "-o", obj]
+        cmd = [HIPCC, "-x", "hip", *DEVICE, *flags, "-c", src, "-o", obj]
     else:
-        cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+        cmd = [HIPCC, *flags, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj, r.stderr
 
 
-def build(verbose=False):
+def build(verbose=False, lib=LIB, defines=()):
+    """Compiles every source and links `lib`.  `defines` (NAME=VALUE strings)
+    override the launch-shape constants of the sources, for tuning builds."""
     os.makedirs(BUILD, exist_ok=True)
     gen_filters()
+    bdir = BUILD if not defines else os.path.join(BUILD, "v_" + "_".join(defines).replace("=", ""))
+    os.makedirs(bdir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
-        results = list(ex.map(_compile, sources()))
+        results = list(ex.map(lambda src: _compile(src, bdir, defines), sources()))
     objs = [o for o, _ in results]
     if verbose:
         for _, err in results:
             if err.strip():
                 sys.stderr.write(err)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -16,8 +16,14 @@ constexpr int kTySyn = 64;    // output rows per synthesis workgroup (levels >= 
 constexpr int kTyFinal = 128; // output rows per final synthesis workgroup
 constexpr int kDiracE = 4;    // pixels in flight per thread in the Dirac part of the analysis
 constexpr int kMaxDiracWg = 2048;
+constexpr int kAnaMaxPhase = 4;          // steps per LDS phase of the analysis (upper bound)
+#ifndef FHS_ANA_LDS_KB
+#define FHS_ANA_LDS_KB 64
+#endif
+constexpr int kAnaLdsBytes = FHS_ANA_LDS_KB * 1024;  // LDS budget of an analysis workgroup (both buffers)
 
 int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+int round64(int n) { return (n + 63) / 64 * 64; }
 
 float *ws_f(const fhs_plan *p, int64_t off) { return reinterpret_cast<float *>(static_cast<char *>(p->ws) + off); }
 double *ws_d(const fhs_plan *p, int64_t off) { return reinterpret_cast<double *>(static_cast<char *>(p->ws) + off); }
@@ -42,6 +48,13 @@ int64_t coef_off(const fhs_plan *p, int b, int j, int s) {  // s: 0 lh, 1 hl, 2 
 int64_t ll_off(const fhs_plan *p, int b) { return p->bands[p->band_first[b] + 3 * p->cfg.levels].off; }
 int64_t dirac_off(const fhs_plan *p) { return p->bands.back().off; }
 
+// LDS words of one phase buffer of the analysis for P steps.
+int ana_lds_buf(const AnaArgs &a, int P) {
+  int words = round64(2 * P * a.lds_row);
+  if (a.mode == 1) words += 4 * P * (a.wpad + a.tpad);
+  return words;
+}
+
 // mode 0: w = Psi^dagger x ; mode 1: l21 dual update of w ; mode 2: theta weights
 int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, const double *mu, double inv_kappa,
                  int mode, void *stream) {
@@ -57,6 +70,7 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     a.mu = mu;
     a.inv_kappa = inv_kappa;
     a.I = p->I;
+    a.theta_bytes = static_cast<int64_t>(p->C) * p->I * 4;
     a.L = p->L;
     a.C = p->C;
     a.Lc = p->Lc;
@@ -64,7 +78,21 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     a.tkx1 = tkx1;
     a.tky = kTkyAna;
     a.mode = mode;
-    int prefix = 0;
+    a.rs = 0;
+    a.lds_row = round64((2 * TKX + kMaxTap - 2) * p->L);
+    a.wpad = round64(TKX * p->L);
+    a.tpad = round64(p->C * TKX);
+    a.P = 1;
+    for (int P = kAnaMaxPhase; P >= 1; P /= 2)
+      if (2 * ana_lds_buf(a, P) * 4 <= kAnaLdsBytes || P == 1) {
+        a.P = P;
+        break;
+      }
+    a.lds_buf = ana_lds_buf(a, a.P);
+    a.lds_wv = round64(2 * a.P * a.lds_row);
+    a.lds_th = a.lds_wv + 4 * a.P * a.wpad;
+    if (2 * a.lds_buf * 4 > 160 * 1024) return fail(FHS_EUNSUPPORTED, "analysis: LDS tile exceeds 160 KB");
+    int tmax = 0;
     for (int b = 0; b < kBases; ++b) {
       AnaBand &B = a.b[b];
       B.in = j == 0 ? x : ws_f(p, p->ws_ll[b][j - 1]);
@@ -79,10 +107,10 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       B.ntap = p->ntap[b];
       for (int s = 0; s < 3; ++s) B.off[s] = coef_off(p, b, j, s);
       B.off[3] = j == levels - 1 ? ll_off(p, b) : -1;
-      a.wg_prefix[b] = prefix;
-      prefix += B.strips * B.yblocks;
+      tmax = std::max(tmax, B.strips * B.yblocks);
     }
-    a.wg_prefix[kBases] = prefix;
+    a.tiles_per_xcd = ceil_div(tmax, 8);
+    a.nbase_wg = 64 * a.tiles_per_xcd;
     if (j == 0) {
       AnaBand &D = a.b[kBases];
       D.in = x;
@@ -93,9 +121,7 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       // grid-stride workgroups for the Dirac band (kDiracE pixels in flight per thread)
       D.strips = std::max(1, std::min(kMaxDiracWg, ceil_div(static_cast<int64_t>(p->cfg.ny) * p->cfg.nx,
                                                             static_cast<int64_t>(kDiracE) * TKX)));
-      prefix += D.strips;
     }
-    a.wg_prefix[kBases + 1] = prefix;
     const int kid = j == 0 ? FHS_K_ANALYSIS_L1 : FHS_K_ANALYSIS;
     prof_begin(p, kid, stream);
     const int rc = launch_analysis(a, nth, j == 0, stream);

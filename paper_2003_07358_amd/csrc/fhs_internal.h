@@ -39,15 +39,23 @@ struct AnaBand {
 };
 
 struct AnaArgs {
-  AnaBand b[kBases + 1];      // [8] = Dirac (elementwise)
-  int wg_prefix[kBases + 2];  // cumulative workgroups per basis
+  AnaBand b[kBases + 1];      // [8] = Dirac (elementwise; strips = its workgroups)
   float *w;
   float *theta;               // read (mode 1) or written (mode 2)
   const double *mu;           // [C] thresholds mu_c (mode 1) or upsilon_c (mode 2)
   double inv_kappa;
   int64_t I;
+  int64_t theta_bytes;        // C * I * 4 (< 2^31)
   int L, C, Lc, Lcp, tkx1, tky;
   int mode;                   // 0: write Psi^dagger x; 1: l21 dual update; 2: l21 weights
+  int P;                      // steps per LDS phase
+  int rs;                     // LDS words per channel of an input row segment (odd)
+  int lds_row;                // L * rs
+  int lds_wv, lds_th;         // offsets (words) of the W and theta areas in a phase buffer
+  int lds_buf;                // words per phase buffer
+  int wpad, tpad;             // words per W / theta segment (multiples of 64)
+  int tiles_per_xcd;          // tiles walked by each XCD
+  int nbase_wg;               // 64 * tiles_per_xcd workgroups for the wavelet bases
 };
 
 // One wavelet basis at one level of the synthesis (levels >= 2): writes the
@@ -125,6 +133,9 @@ struct ClosureArgs {
 
 // ---------------------------------------------------------------- launchers
 int launch_analysis(const AnaArgs &a, int nthreads, bool first, void *stream);
+int launch_analysis_m0(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
+int launch_analysis_m1(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
+int launch_analysis_m2(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
 int launch_synthesis(const SynArgs &a, int nthreads, void *stream);
 int launch_synthesis_final(const SynFinalArgs &a, int nthreads, int group, void *stream);
 int launch_nuc_gram(const NucArgs &a, int nfacets, void *stream);

@@ -67,13 +67,16 @@ __device__ __forceinline__ void drain_loads() { asm volatile("s_waitcnt vmcnt(0)
 // moves that stay in the VALU where possible: DPP quad permutations (lane ^ 1,
 // lane ^ 2), DPP half-row and row mirrors (which pair the two halves of 8 and
 // of 16 lanes), a ds_swizzle xor 16 and, for 64 lanes, a bpermute.
+// (update_dpp with bound_ctrl lets the compiler fold the move into the add:
+// one v_add_f32 with a DPP source)
 __device__ __forceinline__ float dpp_add(float v, int ctrl_tag) {
   int o;
+  const int iv = __float_as_int(v);
   switch (ctrl_tag) {
-    case 0: o = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false); break;   // quad [1,0,3,2]
-    case 1: o = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false); break;   // quad [2,3,0,1]
-    case 2: o = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false); break;  // row half mirror
-    default: o = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false); break; // row mirror
+    case 0: o = __builtin_amdgcn_update_dpp(0, iv, 0xB1, 0xF, 0xF, true); break;   // quad [1,0,3,2]
+    case 1: o = __builtin_amdgcn_update_dpp(0, iv, 0x4E, 0xF, 0xF, true); break;   // quad [2,3,0,1]
+    case 2: o = __builtin_amdgcn_update_dpp(0, iv, 0x141, 0xF, 0xF, true); break;  // row half mirror
+    default: o = __builtin_amdgcn_update_dpp(0, iv, 0x140, 0xF, 0xF, true); break; // row mirror
   }
   return v + __int_as_float(o);
 }

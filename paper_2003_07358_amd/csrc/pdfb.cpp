@@ -82,7 +82,7 @@ int fhs_pdfb_graph_create(const fhs_plan *p, const fhs_pdfb_state *s, int32_t n_
     return fail(FHS_EHIP, "hipStreamCreateWithFlags failed");
   auto *g = new (std::nothrow) fhs_graph;
   if (!g) {
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     return fail(FHS_ENOMEM, "out of host memory");
   }
   int rc = FHS_OK;
@@ -95,9 +95,9 @@ int fhs_pdfb_graph_create(const fhs_plan *p, const fhs_pdfb_state *s, int32_t n_
   }
   if (rc == FHS_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
     rc = fail(FHS_EHIP, "hipGraphInstantiate failed");
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (rc != FHS_OK) {
-    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
     return rc;
   }
@@ -115,8 +115,8 @@ int fhs_graph_launch(const fhs_graph *g, void *stream) {
 
 void fhs_graph_destroy(fhs_graph *g) {
   if (!g) return;
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
 }
 

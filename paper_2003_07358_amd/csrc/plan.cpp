@@ -77,7 +77,7 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   p->C = c.n_sub;
   p->Lc = c.nchan / c.n_sub;
   p->Q = c.qy * c.qx;
-  int lcp = 1;
+  int lcp = 4;  // lanes per sub-cube: a power of two >= L_c, at least 4
   while (lcp < p->Lc) lcp *= 2;
   p->Lcp = lcp;
   p->lc16 = (p->Lc + 15) / 16 * 16;
@@ -163,6 +163,10 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   p->bands.push_back({c.ny, c.nx, off, 0});
   off += static_cast<int64_t>(c.ny) * c.nx;
   p->I = off;
+  if (static_cast<int64_t>(p->C) * p->I * 4 >= (int64_t{1} << 31)) {
+    delete p;
+    return fail(FHS_EUNSUPPORTED, "theta (C * I floats) must be smaller than 2 GiB");
+  }
 
   // workspace: low-low bands of every basis and level but the last, then the
   // nuclear scratch (partial Gram matrices, K matrices, singular values)

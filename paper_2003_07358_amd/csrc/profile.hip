@@ -11,19 +11,19 @@ void prof_begin(const fhs_plan *p, int kid, void *stream) {
   if (p->prof_kernel != kid) return;
   const int n = static_cast<int>(p->prof_events.size()) / 2;
   if (p->prof_next >= n) return;
-  hipEventRecord(static_cast<hipEvent_t>(p->prof_events[2 * p->prof_next]), static_cast<hipStream_t>(stream));
+  (void)hipEventRecord(static_cast<hipEvent_t>(p->prof_events[2 * p->prof_next]), static_cast<hipStream_t>(stream));
 }
 
 void prof_end(const fhs_plan *p, int kid, void *stream) {
   if (p->prof_kernel != kid) return;
   const int n = static_cast<int>(p->prof_events.size()) / 2;
   if (p->prof_next >= n) return;
-  hipEventRecord(static_cast<hipEvent_t>(p->prof_events[2 * p->prof_next + 1]), static_cast<hipStream_t>(stream));
+  (void)hipEventRecord(static_cast<hipEvent_t>(p->prof_events[2 * p->prof_next + 1]), static_cast<hipStream_t>(stream));
   ++p->prof_next;
 }
 
 void prof_release(fhs_plan *p) {
-  for (void *e : p->prof_events) hipEventDestroy(static_cast<hipEvent_t>(e));
+  for (void *e : p->prof_events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   p->prof_events.clear();
   p->prof_next = 0;
   p->prof_kernel = -1;
