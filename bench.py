@@ -122,6 +122,7 @@ def main():
     ap.add_argument("--kernel", default="analysis_l1", help="kernel reported in the roofline entry")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default launch shapes")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (the reference "
                          "dispatch that scales HBM counters read under rocprofv3 --pmc)")
@@ -167,6 +168,15 @@ def main():
         log(f"[bench] calibration copy kernel: {n * 4} bytes read, {n * 4} bytes written")
         del src, dst
 
+    if not args.no_autotune:
+        # launch shapes picked on the workload itself (outside the timed region);
+        # the duals it scribbles on are reset afterwards
+        t0a = time.perf_counter()
+        tuning = plan.autotune(x_d, p_d, w_d, th_d, tb_d, mu_d, mub_d, g_d, reps=3)
+        p_d.zero_()
+        w_d.zero_()
+        torch.cuda.synchronize()
+        log(f"[bench] autotune {time.perf_counter() - t0a:.1f} s: {tuning}")
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
         one_step()
@@ -215,6 +225,7 @@ def main():
         "roofline": {"kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": kb / per_step, "avg_launch_ms": kms / max(launches, 1)},
+        "tuning": plan.tuning,
         "step_hbm": {"algorithmic_bytes": sb, "achieved_GBs": sb / (ms / 1e3) / 1e9,
                      "frac": sb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
     }

@@ -132,6 +132,36 @@ int fhs_plan_band(const fhs_plan *plan, int32_t k, int64_t out[4]);
  * sigma_bar [C] in, mu [C] out, mu_bar [C*Q] out. */
 int fhs_plan_heuristics(const fhs_plan *plan, const double *sigma_bar, double *mu, double *mu_bar);
 
+/* Launch shapes of the kernels.  They change speed, not the computation: the
+ * wavelet outputs are bitwise the same for every valid setting; the nuclear
+ * Gram sums follow the row chunking, so P and G may differ in the last bits.
+ * For a fixed setting every call is bitwise reproducible. */
+typedef struct {
+  int32_t ana_rows[6];     /* coefficient rows per analysis workgroup, per level (8..256) */
+  int32_t ana_phase;       /* upper bound on steps per LDS phase of the analysis (1, 2, 4) */
+  int32_t syn_rows;        /* output rows per synthesis workgroup, levels >= 2 (16..256) */
+  int32_t fin_rows;        /* output rows per level-1 synthesis workgroup (16..512) */
+  int32_t nuc_seg;         /* pixels per staged segment of the nuclear kernels (16, 32, 64) */
+  int32_t nuc_chunk_rows;  /* window rows per nuclear workgroup (>= the plan's minimum) */
+  int32_t concurrent;      /* 1: the nuclear chain runs on a second stream beside the wavelet chain */
+} fhs_tuning;
+
+/* Current launch shapes (defaults after fhs_plan_create). HOST pointer. */
+int fhs_plan_get_tuning(const fhs_plan *plan, fhs_tuning *out);
+/* Replaces the launch shapes; FHS_EINVAL (plan unchanged) if a field is out
+ * of range.  Not to be called while compute calls of the plan are in flight. */
+int fhs_plan_set_tuning(fhs_plan *plan, const fhs_tuning *tuning);
+
+/* Autotuner: times fhs_facet_prox_step for candidate launch shapes, one field
+ * at a time (coordinate descent, `reps` steps per candidate, HIP events on
+ * `stream`), keeps the fastest and returns with the plan set to it.  The
+ * arguments are those of fhs_facet_prox_step; p_inout, w_inout and grad are
+ * overwritten with unspecified values (pass scratch copies).  Synchronises
+ * the host with `stream`; a setup call, not a compute call. */
+int fhs_plan_autotune(fhs_plan *plan, const float *xcheck, float *p_inout, float *w_inout,
+                      const float *theta, const double *theta_bar, const double *mu,
+                      const double *mu_bar, float *grad, int32_t reps, void *stream);
+
 /* Attaches caller-owned device scratch of at least fhs_sizes.workspace_bytes
  * bytes (256-byte aligned).  The plan keeps the pointer, not the memory. */
 int fhs_plan_set_workspace(fhs_plan *plan, void *dev_ptr, int64_t bytes);

@@ -29,6 +29,11 @@ class _Sizes(ctypes.Structure):
                  "workspace_bytes")]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("ana_rows", ctypes.c_int32 * 6)] + [(n, ctypes.c_int32) for n in
+                ("ana_phase", "syn_rows", "fin_rows", "nuc_seg", "nuc_chunk_rows", "concurrent")]
+
+
 class _PdfbState(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("x", "xcheck", "p", "w", "v", "y", "eps", "theta", "theta_bar", "mu", "mu_bar", "grad", "xi")] + \
@@ -49,6 +54,9 @@ SYMBOLS = {
     "fhs_plan_heuristics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "fhs_plan_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "fhs_plan_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
+    "fhs_plan_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning)]),
+    "fhs_plan_autotune": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 8 + [ctypes.c_int32, ctypes.c_void_p]),
     "fhs_sara_analysis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fhs_sara_synthesis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float,
                                           ctypes.c_float, ctypes.c_void_p]),
@@ -175,6 +183,42 @@ class Plan:
         mub = np.zeros(self.sizes["n_facets"])
         _check(self._lib.fhs_plan_heuristics(self._p, _dptr(sb), _dptr(mu), _dptr(mub)))
         return mu, mub
+
+    # ------------------------------------------------------------ launch shapes
+    @property
+    def tuning(self):
+        t = _Tuning()
+        _check(self._lib.fhs_plan_get_tuning(self._p, ctypes.byref(t)))
+        d = {n: getattr(t, n) for n, _ in _Tuning._fields_}
+        d["ana_rows"] = list(t.ana_rows)
+        return d
+
+    @tuning.setter
+    def tuning(self, d):
+        t = _Tuning()
+        _check(self._lib.fhs_plan_get_tuning(self._p, ctypes.byref(t)))
+        for n, v in d.items():
+            if n == "ana_rows":
+                for j, r in enumerate(v):
+                    t.ana_rows[j] = int(r)
+            else:
+                setattr(t, n, int(v))
+        _check(self._lib.fhs_plan_set_tuning(self._p, ctypes.byref(t)))
+
+    def autotune(self, xcheck, p, w, theta, theta_bar, mu, mu_bar, grad, reps=3):
+        """Times candidate launch shapes on these arrays and keeps the fastest
+        (p, w and grad are overwritten: pass scratch copies)."""
+        import torch
+        self._need_ws()
+        s = self.sizes
+        _check(self._lib.fhs_plan_autotune(
+            self._p, self._t(xcheck, s["n_x"], torch.float32, "xcheck"),
+            self._t(p, s["n_p"], torch.float32, "p"), self._t(w, s["n_w"], torch.float32, "w"),
+            self._t(theta, s["n_theta"], torch.float32, "theta"),
+            self._t(theta_bar, s["n_theta_bar"], torch.float64, "theta_bar"),
+            self._t(mu, self.C, torch.float64, "mu"), self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"),
+            self._t(grad, s["n_x"], torch.float32, "grad"), int(reps), _stream(xcheck)))
+        return self.tuning
 
     # ------------------------------------------------------------ device side
     def attach_workspace(self, device="cuda"):

@@ -2,6 +2,8 @@
 // No device allocation, no host synchronisation: every call only enqueues
 // kernels on the caller's stream, so a sequence of calls can be captured in a
 // HIP graph.
+#include <hip/hip_runtime.h>
+
 #include <algorithm>
 #include <cstring>
 
@@ -11,16 +13,13 @@ using namespace fhs;
 
 namespace {
 
-constexpr int kTkyAna = 64;   // coefficient rows per analysis workgroup
-constexpr int kTySyn = 64;    // output rows per synthesis workgroup (levels >= 2)
-constexpr int kTyFinal = 128; // output rows per final synthesis workgroup
 constexpr int kDiracE = 4;    // pixels in flight per thread in the Dirac part of the analysis
 constexpr int kMaxDiracWg = 2048;
-constexpr int kAnaMaxPhase = 4;          // steps per LDS phase of the analysis (upper bound)
 #ifndef FHS_ANA_LDS_KB
 #define FHS_ANA_LDS_KB 64
 #endif
-constexpr int kAnaLdsBytes = FHS_ANA_LDS_KB * 1024;  // LDS budget of an analysis workgroup (both buffers)
+constexpr int kAnaLdsBytes = FHS_ANA_LDS_KB * 1024;
+constexpr int kAnaThreads = FHS_ANA_THREADS;  // upper bound on analysis workgroup size  // LDS budget of an analysis workgroup (both buffers)
 
 int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 int round64(int n) { return (n + 63) / 64 * 64; }
@@ -28,10 +27,10 @@ int round64(int n) { return (n + 63) / 64 * 64; }
 float *ws_f(const fhs_plan *p, int64_t off) { return reinterpret_cast<float *>(static_cast<char *>(p->ws) + off); }
 double *ws_d(const fhs_plan *p, int64_t off) { return reinterpret_cast<double *>(static_cast<char *>(p->ws) + off); }
 
-int thread_cfg(const fhs_plan *p, int *tkx1, int *nthreads) {
+int thread_cfg(const fhs_plan *p, int *tkx1, int *nthreads, int max_threads = 256) {
   const int per = p->Lcp * p->C;
   if (per > 256) return fail(FHS_EUNSUPPORTED, "sub-cubes x padded channels per sub-cube exceed 256");
-  *tkx1 = std::max(1, 256 / per);
+  *tkx1 = std::max(1, max_threads / per);
   *nthreads = *tkx1 * per;
   return FHS_OK;
 }
@@ -59,7 +58,7 @@ int ana_lds_buf(const AnaArgs &a, int P) {
 int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, const double *mu, double inv_kappa,
                  int mode, void *stream) {
   int tkx1, nth;
-  if (int rc = thread_cfg(p, &tkx1, &nth)) return rc;
+  if (int rc = thread_cfg(p, &tkx1, &nth, kAnaThreads)) return rc;
   const int TKX = tkx1;
   const int levels = p->cfg.levels;
   for (int j = 0; j < levels; ++j) {
@@ -76,14 +75,14 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     a.Lc = p->Lc;
     a.Lcp = p->Lcp;
     a.tkx1 = tkx1;
-    a.tky = kTkyAna;
+    a.tky = p->tune.ana_rows[j];
     a.mode = mode;
     a.rs = 0;
     a.lds_row = round64((2 * TKX + kMaxTap - 2) * p->L);
     a.wpad = round64(TKX * p->L);
     a.tpad = round64(p->C * TKX);
     a.P = 1;
-    for (int P = kAnaMaxPhase; P >= 1; P /= 2)
+    for (int P = p->tune.ana_phase; P >= 1; P /= 2)
       if (2 * ana_lds_buf(a, P) * 4 <= kAnaLdsBytes || P == 1) {
         a.P = P;
         break;
@@ -103,7 +102,7 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       B.Ky = p->Ky[b][j];
       B.Kx = p->Kx[b][j];
       B.strips = ceil_div(B.Kx, TKX);
-      B.yblocks = ceil_div(B.Ky, kTkyAna);
+      B.yblocks = ceil_div(B.Ky, a.tky);
       B.ntap = p->ntap[b];
       for (int s = 0; s < 3; ++s) B.off[s] = coef_off(p, b, j, s);
       B.off[3] = j == levels - 1 ? ll_off(p, b) : -1;
@@ -144,7 +143,7 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
     s.C = p->C;
     s.Lc = p->Lc;
     s.tk = tk;
-    s.ty = kTySyn;
+    s.ty = p->tune.syn_rows;
     int prefix = 0;
     for (int b = 0; b < kBases; ++b) {
       SynBand &B = s.b[b];
@@ -158,7 +157,7 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
       B.ny = p->in_ny[b][j];
       B.nx = p->in_nx[b][j];
       B.strips = ceil_div((B.nx + 1) / 2, tk);
-      B.yblocks = ceil_div(B.ny, kTySyn);
+      B.yblocks = ceil_div(B.ny, s.ty);
       B.ntap = p->ntap[b];
       s.wg_prefix[b] = prefix;
       prefix += B.strips * B.yblocks;
@@ -194,9 +193,9 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
   f.C = p->C;
   f.Lc = p->Lc;
   f.tk = tk;
-  f.ty = kTyFinal;
+  f.ty = p->tune.fin_rows;
   f.strips = ceil_div((p->cfg.nx + 1) / 2, tk);
-  f.yblocks = ceil_div(p->cfg.ny, kTyFinal);
+  f.yblocks = ceil_div(p->cfg.ny, f.ty);
   for (int grp = 0; grp < 2; ++grp) {
     const int kid = grp == 0 ? FHS_K_SYNTH_FINAL_A : FHS_K_SYNTH_FINAL_B;
     prof_begin(p, kid, stream);
@@ -233,9 +232,12 @@ void fill_geom(const fhs_plan *p, NucGeom &g) {
   g.p_sub = p->p_sub;
 }
 
-// mode 0: dual update of p (+ gather); mode 1: weights only
+int run_gather(const fhs_plan *p, const float *pdual, float *grad, double zeta, float beta, void *stream);
+
+// mode 0: dual update of p (+ gather unless no_gather); mode 1: weights only
 int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *theta_bar, const double *mu_bar,
-                double zeta, double *theta_bar_out, float *grad, float beta, int mode, void *stream) {
+                double zeta, double *theta_bar_out, float *grad, float beta, int mode, void *stream,
+                bool no_gather = false) {
   NucArgs a;
   std::memset(&a, 0, sizeof(a));
   fill_geom(p, a.g);
@@ -248,14 +250,15 @@ int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *t
   a.mu_bar = mu_bar;
   a.theta_bar_out = theta_bar_out;
   a.inv_zeta = 1.0 / zeta;
-  a.chunks = p->gram_chunks;
-  a.chunk_rows = p->gram_chunk_rows;
+  a.chunk_wrows = p->tune.nuc_chunk_rows;
+  a.chunks = ceil_div(p->max_hy, a.chunk_wrows);  // <= p->gram_chunks (the workspace's slots)
+  a.seg = p->tune.nuc_seg;
   a.lc16 = p->lc16;
   a.mode = mode;
   const int nf = static_cast<int>(p->facets.size());
   int rc;
   prof_begin(p, FHS_K_NUC_GRAM, stream);
-  rc = launch_nuc_gram(a, nf, stream);
+  rc = launch_nuc_gram(a, p->Q, stream);
   prof_end(p, FHS_K_NUC_GRAM, stream);
   if (rc) return rc;
   prof_begin(p, FHS_K_NUC_EIG, stream);
@@ -264,18 +267,23 @@ int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *t
   if (rc) return rc;
   if (mode == 1) return FHS_OK;
   prof_begin(p, FHS_K_NUC_RECON, stream);
-  rc = launch_nuc_recon(a, nf, ceil_div(p->max_rows, 64), stream);
+  rc = launch_nuc_recon(a, p->Q, stream);
   prof_end(p, FHS_K_NUC_RECON, stream);
   if (rc) return rc;
+  if (no_gather) return FHS_OK;
+  return run_gather(p, pdual, grad, zeta, beta, stream);
+}
+
+int run_gather(const fhs_plan *p, const float *pdual, float *grad, double zeta, float beta, void *stream) {
   GatherArgs ga;
   std::memset(&ga, 0, sizeof(ga));
-  ga.g = a.g;
+  fill_geom(p, ga.g);
   ga.p = pdual;
   ga.grad = grad;
   ga.zeta = zeta;
   ga.beta = beta;
   prof_begin(p, FHS_K_NUC_GATHER, stream);
-  rc = launch_nuc_gather(ga, stream);
+  const int rc = launch_nuc_gather(ga, stream);
   prof_end(p, FHS_K_NUC_GATHER, stream);
   return rc;
 }
@@ -320,8 +328,24 @@ int fhs_facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, fl
   if (!xcheck || !pdual || !w || !theta || !theta_bar || !mu || !mu_bar || !grad)
     return fail(FHS_EINVAL, "fhs_facet_prox_step: null array");
   if (!(zeta > 0) || !(kappa > 0)) return fail(FHS_EINVAL, "zeta and kappa must be positive");
-  if (int rc = fhs_l21_dual_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream)) return rc;
-  return run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, stream);
+  if (!p->side || !p->tune.concurrent) {
+    if (int rc = fhs_l21_dual_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream)) return rc;
+    return run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, stream);
+  }
+  // The two dual updates are independent until the gather: the nuclear
+  // chain (Gram, eigendecomposition, reconstruction) runs on the plan's side
+  // stream beside the wavelet chain, and the gather waits for both.
+  hipStream_t s0 = static_cast<hipStream_t>(stream), s1 = static_cast<hipStream_t>(p->side);
+  hipEvent_t fork = static_cast<hipEvent_t>(p->ev_fork), join = static_cast<hipEvent_t>(p->ev_join);
+  if (hipEventRecord(fork, s0) != hipSuccess || hipStreamWaitEvent(s1, fork, 0) != hipSuccess)
+    return fail(FHS_EHIP, "fork to the side stream failed");
+  int rc = run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, s1, true);
+  const bool joined = hipEventRecord(join, s1) == hipSuccess;
+  if (rc == FHS_OK) rc = fhs_l21_dual_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream);
+  if (!joined || hipStreamWaitEvent(s0, join, 0) != hipSuccess)
+    return rc ? rc : fail(FHS_EHIP, "join of the side stream failed");
+  if (rc) return rc;
+  return run_gather(p, pdual, grad, zeta, 1.0f, stream);
 }
 
 int fhs_reweight(const fhs_plan *p, const float *x, const double *upsilon, const double *upsilon_bar, float *theta,

@@ -91,13 +91,15 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
   const int ln = threadIdx.x & 63;
   const int64_t seg0 = static_cast<int64_t>(col0) * L;  // first float of a row segment
   const int segn = NC * L;                               // floats of a row segment
-  // theta gather: lane ln -> (sub-cube ln / TKX, column kx0 + ln % TKX); C * TKX <= 64
-  int th_voff;
-  {
-    const int cc = ln / TKX, kk = ln - cc * TKX;
-    th_voff = (cc < C && kx0 + kk < B.Kx) ? static_cast<int>((static_cast<int64_t>(cc) * A.I + kx0 + kk) * 4)
-                                          : static_cast<int>(0x80000000u);
+  // theta gather: word i = 64 j + ln -> (sub-cube i / TKX, column kx0 + i % TKX); C * TKX <= 128
+  int th_voff[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int i = 64 * j + ln, cc = i / TKX, kk = i - cc * TKX;
+    th_voff[j] = (cc < C && kx0 + kk < B.Kx) ? static_cast<int>((static_cast<int64_t>(cc) * A.I + kx0 + kk) * 4)
+                                             : static_cast<int>(0x80000000u);
   }
+  const int nth_chunks = (C * TKX + 63) / 64;
 
   auto issue_phase = [&](int ph) __attribute__((always_inline)) {
     if (wv >= nwv) return;
@@ -125,8 +127,11 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
         // theta of the same rows for every sub-cube: a gather
         const fhs_int32x4 tr = buffer_rsrc(A.theta, static_cast<unsigned>(A.theta_bytes));
         float *tdst = buf + A.lds_th + (4 * k + s) * A.tpad;
-        fhs_raw_buffer_load_lds(tr, lds_ptr(tdst), 4, th_voff,
-                                static_cast<int>((boff + static_cast<int64_t>(ky) * B.Kx) * 4), 0, 0);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          if (j < nth_chunks)
+            fhs_raw_buffer_load_lds(tr, lds_ptr(tdst + 64 * j), 4, th_voff[j],
+                                    static_cast<int>((boff + static_cast<int64_t>(ky) * B.Kx) * 4), 0, 0);
       }
     }
   };
@@ -261,7 +266,7 @@ __device__ __forceinline__ void dirac(const AnaArgs &A, const AnaBand &B, int wg
 // FIRST: level 1 (reads the cube, also handles the Dirac basis); a separate
 // instantiation so that its launches are timed and profiled on their own.
 template <bool FIRST, int MODE, int LCP>
-__global__ void __launch_bounds__(256) kernel(AnaArgs A) {
+__global__ void __launch_bounds__(FHS_ANA_THREADS) kernel(AnaArgs A) {
   extern __shared__ float smem[];
   const int id = blockIdx.x;
   if (id < A.nbase_wg) {

@@ -15,6 +15,9 @@ constexpr int kMaxTap = 16;        // db8 has 16 taps
 constexpr int kMaxLevels = 6;
 constexpr int kMaxFacetAxis = 64;  // facets per axis
 constexpr int kMaxLc = 64;         // channels per sub-cube
+#ifndef FHS_ANA_THREADS
+#define FHS_ANA_THREADS 512        // analysis workgroup size bound (256 or 512)
+#endif
 
 // ---------------------------------------------------------------- error state
 void set_error(const std::string &msg);
@@ -104,8 +107,9 @@ struct NucArgs {
   const double *mu_bar;      // [facets] (or upsilon_bar for the weights)
   double *theta_bar_out;     // reweighting output or null
   double inv_zeta;
-  int chunks;                // row chunks per facet (grid.x of the Gram kernel)
-  int chunk_rows;            // rows per chunk
+  int chunks;                // window-row chunks per facet (grid.x of the Gram / reconstruction kernels)
+  int chunk_wrows;           // window rows per chunk
+  int seg;                   // pixels per staged segment
   int lc16;                  // Lc rounded up to 16
   int mode;                  // 0: dual update; 1: weights only
 };
@@ -138,9 +142,9 @@ int launch_analysis_m1(const AnaArgs &a, int nthreads, bool first, size_t lds, v
 int launch_analysis_m2(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
 int launch_synthesis(const SynArgs &a, int nthreads, void *stream);
 int launch_synthesis_final(const SynFinalArgs &a, int nthreads, int group, void *stream);
-int launch_nuc_gram(const NucArgs &a, int nfacets, void *stream);
+int launch_nuc_gram(const NucArgs &a, int nspatial, void *stream);
 int launch_nuc_eig(const NucArgs &a, int nfacets, void *stream);
-int launch_nuc_recon(const NucArgs &a, int nfacets, int rowblocks, void *stream);
+int launch_nuc_recon(const NucArgs &a, int nspatial, void *stream);
 int launch_nuc_gather(const GatherArgs &a, void *stream);
 int launch_closure(const ClosureArgs &a, void *stream);
 
@@ -171,9 +175,15 @@ struct fhs_plan {
   int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_red = 0, ws_factor = 0, ws_bytes = 0;
   int64_t red_ppb = 0;                     // closure: pixels per block
   int red_blocks = 0;                      // closure: blocks
-  int gram_chunks = 0, gram_chunk_rows = 0, max_rows = 0;
+  int gram_chunks = 0, max_rows = 0;       // Gram partial slots per facet (workspace capacity)
+  int max_hy = 0, max_hx = 0;               // largest window
+  int nuc_chunk_min = 1;                    // smallest window-row chunk the workspace allows
+  fhs_tuning tune{};                        // launch shapes
   void *ws = nullptr;
   int64_t ws_given = 0;
+  // second stream and fork / join events: the nuclear chain runs beside the
+  // wavelet chain (created when the workspace is attached; null = one stream)
+  void *side = nullptr, *ev_fork = nullptr, *ev_join = nullptr;
   // optional per-kernel event timing (diagnostics)
   mutable int prof_kernel = -1;
   mutable std::vector<void *> prof_events;  // hipEvent_t pairs
@@ -181,6 +191,8 @@ struct fhs_plan {
 };
 
 namespace fhs {
+// LDS bytes of one nuclear reconstruction workgroup for segments of S pixels.
+int64_t nuc_recon_lds(const fhs_plan *p, int S);
 // Records the start / stop events around one launch when profiling `kid`.
 void prof_begin(const fhs_plan *p, int kid, void *stream);
 void prof_end(const fhs_plan *p, int kid, void *stream);

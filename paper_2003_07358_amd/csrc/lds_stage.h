@@ -30,6 +30,21 @@ __device__ __forceinline__ fhs_int32x4 buffer_rsrc(const void *base, unsigned by
 
 __device__ __forceinline__ int round_up(int n, int m) { return (n + m - 1) / m * m; }
 
+__device__ __forceinline__ __attribute__((address_space(3))) unsigned int *lds_words(const float *p) {
+  return reinterpret_cast<__attribute__((address_space(3))) unsigned int *>(reinterpret_cast<uintptr_t>(p));
+}
+
+// The full waves of the workgroup copy floats [0, n) of src into dst (LDS),
+// 64-float chunks spread over the waves; lanes past n do not write.
+__device__ __forceinline__ void copy_span(const float *src, int n, float *dst) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nwv = blockDim.x >> 6;
+  if (wv >= nwv || n <= 0) return;
+  const fhs_int32x4 rsrc = buffer_rsrc(src, static_cast<unsigned>(n) * 4u);
+  const int ln = threadIdx.x & 63;
+  for (int j = wv * 64; j < n; j += nwv * 64)
+    if (j + ln < n) fhs_raw_buffer_load_lds(rsrc, lds_words(dst + j), 4, (j + ln) * 4, 0, 0, 0);
+}
+
 // One wave copies floats [seg0, seg0 + n) of `row` (zero outside [0, rowlen),
 // or everywhere when !valid) into dst[0 .. n); dst must hold round_up(n, 64)
 // floats (the lanes past n write zeros there).

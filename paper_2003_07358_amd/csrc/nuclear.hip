@@ -20,12 +20,12 @@
 #include <hip/hip_runtime.h>
 
 #include "fhs_internal.h"
+#include "lds_stage.h"
 
 namespace fhs {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int kRB = 64;  // facet rows staged in LDS per step
 
 struct FacetView {
   int c, sy, sx, wy0, wx0, hy, hx;
@@ -57,98 +57,157 @@ __device__ __forceinline__ double ramp(int i, int s, int Q, int o, int len) {
   return 1.0;
 }
 
-// Stages rows [r0, r0 + kRB) of Z (FP64, zero padded to W columns) into LDS.
-// The first kRB threads resolve each row's pixel and window weight once
-// (rinfo_pix / rinfo_d, kRB entries each); every element then needs no
-// division.  The caller synchronises before and after.
-template <int W>
-__device__ __forceinline__ void stage_z(const NucArgs &A, const FacetView &F, int64_t r0, int64_t r_end, double *zs,
-                                       int64_t *rinfo_pix, double *rinfo_d) {
+// ---------------------------------------------------------------- staging
+// A workgroup owns one spatial facet q and a chunk of its window rows, for
+// every sub-cube at once (the cube is read once, whatever C).  It walks the
+// chunk in segments of S consecutive pixels of one window row: the segment's
+// X (S x L floats, one contiguous run of HBM) and, per sub-cube, its P rows
+// (S x L_c floats, contiguous) are copied HBM -> LDS by buffer loads with LDS
+// destination, one segment ahead into a double buffer; the window weight of
+// each pixel is computed into LDS at the same time.
+struct Seg {
+  int y, s0, n;  // window row, first pixel of the segment, pixels in it
+};
+
+__device__ __forceinline__ Seg seg_of(int i, int y0, int nsx, int S, int hx) {
+  Seg sg;
+  sg.y = y0 + i / nsx;
+  sg.s0 = (i - (i / nsx) * nsx) * S;
+  sg.n = min(S, hx - sg.s0);
+  return sg;
+}
+
+// words of one staging buffer: X [S][L] then P [C][S][L_c]
+__device__ __forceinline__ int stage_words(int S, int L) { return 2 * S * L; }
+
+__device__ __forceinline__ void issue_seg(const NucArgs &A, const FacetView &F, const Seg &sg, float *buf, double *dsh,
+                                          bool with_p) {
   const NucGeom &g = A.g;
-  if (threadIdx.x < kRB) {
-    const int64_t r = r0 + threadIdx.x;
-    int64_t pix = -1;
-    double d = 0.0;
-    if (r < r_end) {
-      const int ri = static_cast<int>(r);  // facet rows fit in 32 bits
-      const int yy = ri / F.hx, xx = ri - yy * F.hx;
-      d = ramp(yy, F.sy, g.qy, g.oy, F.hy) * ramp(xx, F.sx, g.qx, g.ox, F.hx);
-      pix = static_cast<int64_t>(F.wy0 + yy) * g.nx + (F.wx0 + xx);
-    }
-    rinfo_pix[threadIdx.x] = pix;
-    rinfo_d[threadIdx.x] = d;
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < kRB * W; idx += blockDim.x) {
-    const int rr = idx / W, l = idx % W;
-    const int64_t pix = rinfo_pix[rr];
-    double z = 0.0;
-    if (pix >= 0 && l < g.Lc) {
-      const double xv = static_cast<double>(A.x[pix * g.L + F.c + l * g.C]);
-      const double pv = A.p ? static_cast<double>(A.p[F.poff + (r0 + rr) * g.Lc + l]) : 0.0;
-      z = pv + rinfo_d[rr] * xv;
-    }
-    zs[rr * (W + 1) + l] = z;
+  const int S = A.seg, L = g.L, Lc = g.Lc;
+  copy_span(A.x + (static_cast<int64_t>(F.wy0 + sg.y) * g.nx + F.wx0 + sg.s0) * L, sg.n * L, buf);
+  if (with_p)
+    for (int c = 0; c < g.C; ++c)
+      copy_span(A.p + c * g.p_sub + F.poff + (static_cast<int64_t>(sg.y) * F.hx + sg.s0) * Lc, sg.n * Lc,
+                buf + S * L + c * S * Lc);
+  if (threadIdx.x < S) {
+    const int i = threadIdx.x;
+    dsh[i] = i < sg.n ? ramp(sg.y, F.sy, g.qy, g.oy, F.hy) * ramp(sg.s0 + i, F.sx, g.qx, g.ox, F.hx) : 0.0;
   }
 }
 
-template <int NB>
-__global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
-  constexpr int W = NB * 16;
-  constexpr int NPAIR = NB * (NB + 1) / 2;
-  constexpr int PPW = (NPAIR + 3) / 4;
-  __shared__ double zs[kRB * (W + 1)];
-  __shared__ int64_t rinfo_pix[kRB];
-  __shared__ double rinfo_d[kRB];
-  const int f = blockIdx.y, chunk = blockIdx.x;
-  const FacetView F = facet_view(A.g, f);
-  const int64_t r_begin = static_cast<int64_t>(chunk) * A.chunk_rows;
-  if (r_begin >= F.rows) return;
-  const int64_t r_end = min(r_begin + A.chunk_rows, F.rows);
-  const int wave = threadIdx.x / 64, ln = threadIdx.x % 64;
-  int bi[PPW], bj[PPW];
-  bool act[PPW];
-#pragma unroll
-  for (int t = 0; t < PPW; ++t) {
-    const int idx = wave + 4 * t;
-    act[t] = idx < NPAIR;
-    int k = 0;
-    bi[t] = bj[t] = 0;
-    for (int a = 0; a < NB; ++a)
-      for (int b = a; b < NB; ++b) {
-        if (k == idx) {
-          bi[t] = a;
-          bj[t] = b;
-        }
-        ++k;
-      }
-  }
-  v4d acc[PPW];
-#pragma unroll
-  for (int t = 0; t < PPW; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+// Z_c[r][ch] = P_c[r][ch] + D_r X[r][c + ch C] in FP64 (0 outside the segment
+// and beyond L_c).
+__device__ __forceinline__ double zval(const NucArgs &A, const float *buf, const double *dsh, int n, bool with_p,
+                                       int c, int r, int ch) {
+  const NucGeom &g = A.g;
+  if (r >= n || ch >= g.Lc) return 0.0;
+  const int S = A.seg, L = g.L;
+  const double xv = static_cast<double>(buf[r * L + c + ch * g.C]);
+  const double pv = with_p ? static_cast<double>(buf[S * L + (c * S + r) * g.Lc + ch]) : 0.0;
+  return fma(dsh[r], xv, pv);
+}
 
-  for (int64_t rb = r_begin; rb < r_end; rb += kRB) {
-    __syncthreads();
-    stage_z<W>(A, F, rb, r_end, zs, rinfo_pix, rinfo_d);
-    __syncthreads();
-#pragma unroll 4
-    for (int k4 = 0; k4 < kRB / 4; ++k4) {
-      const double *row = zs + (k4 * 4 + ln / 16) * (W + 1) + (ln % 16);
+constexpr int kMaxSeg = 64;  // pixels per segment (upper bound)
+
+// block pairs (bi <= bj) of NB 16-channel blocks
+template <int NB>
+struct Pairs {
+  static constexpr int n = NB * (NB + 1) / 2;
+};
+
+// Sub-cubes per Gram workgroup: about ten block pairs of accumulators.
+template <int NB>
+constexpr int gram_subcubes() {
+  return Pairs<NB>::n >= 10 ? 1 : 10 / Pairs<NB>::n;
+}
+
+// Partial Grams of the chunk for sub-cubes [K blockIdx.z, K blockIdx.z + K).
+// Wave w takes the groups of four rows k4 = w mod 4 of every segment; per row
+// group and sub-cube the NB 16-channel columns of Z are formed once and feed
+// the NB (NB + 1) / 2 block pairs.  The four waves' partials are summed in LDS
+// in a fixed order at the end.
+template <int NB, int K>
+__global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
+  using PR = Pairs<NB>;
+  extern __shared__ float sm[];
+  __shared__ double dsh[2][kMaxSeg];
+  const NucGeom &g = A.g;
+  const int q = blockIdx.y, chunk = blockIdx.x, Q = g.qy * g.qx;
+  const FacetView F = facet_view(g, q);
+  const int y0 = chunk * A.chunk_wrows;
+  if (y0 >= F.hy) return;
+  const int y1 = min(y0 + A.chunk_wrows, F.hy);
+  const int S = A.seg, L = g.L;
+  const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;
+  const int BUF = stage_words(S, L);
+  const bool with_p = A.p != nullptr;
+  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int c0 = blockIdx.z * K, nc = min(K, g.C - c0);
+  v4d acc[K][PR::n];
 #pragma unroll
-      for (int t = 0; t < PPW; ++t)
-        if (act[t]) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * bi[t]], row[16 * bj[t]], acc[t], 0, 0, 0);
+  for (int kc = 0; kc < K; ++kc)
+#pragma unroll
+    for (int t = 0; t < PR::n; ++t) acc[kc][t] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  issue_seg(A, F, seg_of(0, y0, nsx, S, F.hx), sm, dsh[0], with_p);
+  for (int i = 0; i < nseg; ++i) {
+    wait_loads_and_sync();
+    if (i + 1 < nseg) issue_seg(A, F, seg_of(i + 1, y0, nsx, S, F.hx), sm + ((i + 1) & 1) * BUF, dsh[(i + 1) & 1], with_p);
+    const float *buf = sm + (i & 1) * BUF;
+    const double *d = dsh[i & 1];
+    const int n = seg_of(i, y0, nsx, S, F.hx).n;
+    for (int k4 = wave; k4 < S / 4; k4 += 4) {
+      const int r = 4 * k4 + ln / 16;
+      const bool rv = r < n;
+      const double dr = d[r];
+#pragma unroll
+      for (int kc = 0; kc < K; ++kc) {
+        if (kc < nc) {
+          // Z[r][ch] = P_c[r][ch] + D_r X[r][c + ch C], ch = 16 b + (ln % 16)
+          const int c = c0 + kc, ch0 = ln & 15;
+          const float *xr = buf + r * L + c + ch0 * g.C;
+          const float *pr = buf + S * L + (c * S + r) * g.Lc + ch0;
+          double z[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const bool ok = rv && 16 * b + ch0 < g.Lc;
+            const double pv = with_p ? static_cast<double>(pr[16 * b]) : 0.0;
+            z[b] = ok ? fma(dr, static_cast<double>(xr[16 * b * g.C]), pv) : 0.0;
+          }
+          int t = 0;
+#pragma unroll
+          for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = bi; bj < NB; ++bj, ++t)
+              acc[kc][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(z[bi], z[bj], acc[kc][t], 0, 0, 0);
+        }
+      }
     }
   }
-  double *out = A.gram + (static_cast<int64_t>(f) * A.chunks + chunk) * A.lc16 * A.lc16;
+  drain_loads();
+  // fixed-order sum of the four waves' partials, block pair by block pair
+  double *red = reinterpret_cast<double *>(sm);
 #pragma unroll
-  for (int t = 0; t < PPW; ++t)
-    if (act[t])
+  for (int kc = 0; kc < K; ++kc) {
+    if (kc < nc) {  // uniform
+      int t = 0;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        // v_mfma_f64_16x16x4f64 result layout: lane holds D[4 v + lane / 16][lane % 16]
-        const int i = 16 * bi[t] + 4 * v + ln / 16, j = 16 * bj[t] + ln % 16;
-        out[i * A.lc16 + j] = acc[t][v];
-      }
+      for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < NB; ++bj, ++t) {
+          __syncthreads();
+#pragma unroll
+          for (int v = 0; v < 4; ++v) red[wave * 256 + v * 64 + ln] = acc[kc][t][v];
+          __syncthreads();
+          const int e = threadIdx.x, v = e >> 6, l = e & 63;
+          const double sum = red[e] + red[256 + e] + red[512 + e] + red[768 + e];
+          // v_mfma_f64_16x16x4f64 result layout: lane l holds D[4 v + l / 16][l % 16]
+          const int ii = 16 * bi + 4 * v + l / 16, jj = 16 * bj + (l & 15);
+          const int f = (c0 + kc) * Q + q;
+          A.gram[(static_cast<int64_t>(f) * A.chunks + chunk) * A.lc16 * A.lc16 + ii * A.lc16 + jj] = sum;
+        }
+    }
+  }
 }
 
 __device__ __forceinline__ void rr_pair(int r, int k, int n2, int &p, int &q) {
@@ -186,7 +245,7 @@ __global__ void __launch_bounds__(256) nuc_eig_kernel(NucArgs A) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int n = g.Lc, n2 = n + (n & 1);
   const FacetView F = facet_view(g, f);
-  const int nch = static_cast<int>((F.rows + A.chunk_rows - 1) / A.chunk_rows);
+  const int nch = (F.hy + A.chunk_wrows - 1) / A.chunk_wrows;
   const double *gp = A.gram + static_cast<int64_t>(f) * A.chunks * A.lc16 * A.lc16;
   for (int idx = tid; idx < n2 * n2; idx += nth) {
     const int i = idx / n2, j = idx - (idx / n2) * n2;
@@ -285,98 +344,210 @@ __global__ void __launch_bounds__(256) nuc_eig_kernel(NucArgs A) {
   }
 }
 
+// P_c <- Z_c K_c for every sub-cube, segment by segment (staging as in the
+// Gram kernel).  Work items (sub-cube, 16-row block, 16-channel block) are
+// spread over the waves; each is NB * 4 FP64 MFMAs with K_c read from LDS.
+// The result goes to an LDS tile first and then to HBM as contiguous runs.
 template <int NB>
 __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
   constexpr int W = NB * 16;
-  __shared__ double Ks[W * (W + 1)];
-  __shared__ double zs[kRB * (W + 1)];
-  __shared__ int64_t rinfo_pix[kRB];
-  __shared__ double rinfo_d[kRB];
-  const int f = blockIdx.y;
-  const FacetView F = facet_view(A.g, f);
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kRB;
-  if (r0 >= F.rows) return;
-  const double *K = A.kmat + static_cast<int64_t>(f) * A.lc16 * A.lc16;
-  for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
-    const int i = idx / W, j = idx - (idx / W) * W;
-    Ks[i * (W + 1) + j] = K[i * A.lc16 + j];
+  extern __shared__ float sm[];
+  __shared__ double dsh[2][kMaxSeg];
+  const NucGeom &g = A.g;
+  const int q = blockIdx.y, chunk = blockIdx.x, Q = g.qy * g.qx;
+  const FacetView F = facet_view(g, q);
+  const int y0 = chunk * A.chunk_wrows;
+  if (y0 >= F.hy) return;
+  const int y1 = min(y0 + A.chunk_wrows, F.hy);
+  const int S = A.seg, L = g.L, Lc = g.Lc, C = g.C;
+  const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;
+  const int BUF = stage_words(S, L);
+  // LDS: K_c [C][W][W + 1] doubles, then two staging buffers, then the output tile [C][S][Lc]
+  double *Ks = reinterpret_cast<double *>(sm);
+  float *stage = sm + 2 * C * W * (W + 1);
+  float *outt = stage + 2 * BUF;
+  for (int idx = threadIdx.x; idx < C * W * W; idx += blockDim.x) {
+    const int c = idx / (W * W), r = idx - c * W * W, i = r / W, j = r - (r / W) * W;
+    Ks[(c * W + i) * (W + 1) + j] = A.kmat[static_cast<int64_t>(c * Q + q) * A.lc16 * A.lc16 + i * A.lc16 + j];
   }
-  stage_z<W>(A, F, r0, F.rows, zs, rinfo_pix, rinfo_d);
-  __syncthreads();
-  const int wave = threadIdx.x / 64, ln = threadIdx.x % 64;
-  const int nb = wave;  // 16-row block of the 64 staged rows
-  const int64_t r = r0 + 16 * nb + ln % 16;
+  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int nrb = S / 16, ntask = C * nrb;
+
+  issue_seg(A, F, seg_of(0, y0, nsx, S, F.hx), stage, dsh[0], true);
+  for (int i = 0; i < nseg; ++i) {
+    wait_loads_and_sync();
+    if (i + 1 < nseg) issue_seg(A, F, seg_of(i + 1, y0, nsx, S, F.hx), stage + ((i + 1) & 1) * BUF, dsh[(i + 1) & 1], true);
+    const float *buf = stage + (i & 1) * BUF;
+    const double *d = dsh[i & 1];
+    const Seg sg = seg_of(i, y0, nsx, S, F.hx);
+    // tasks: (sub-cube, 16-row block) with Z's W / 4 slices formed once for
+    // every 16-channel output block; when there are fewer such tasks than
+    // waves, (sub-cube, row block, channel block) so that every wave works
+    const bool split = ntask < 4;
+    const int ntk = split ? ntask * NB : ntask;
+    for (int t = wave; t < ntk; t += 4) {
+      const int tt = split ? t / NB : t;
+      const int c = tt / nrb, nb = tt - c * nrb;
+      const int mb0 = split ? t - tt * NB : 0, mb1 = split ? mb0 + 1 : NB;
+      const int r = 16 * nb + (ln & 15);
+      double z[W / 4];
 #pragma unroll
-  for (int mb = 0; mb < NB; ++mb) {
-    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int kk = 0; kk < W / 4; ++kk) z[kk] = zval(A, buf, d, sg.n, true, c, r, 4 * kk + ln / 16);
 #pragma unroll
-    for (int kk = 0; kk < W / 4; ++kk) {
-      const int k = 4 * kk + ln / 16;
-      // A[m][k] = K[k][m], B[k][n] = Z[n][k]  ->  D[m][n] = (Z K)[n][m]
-      const double a = Ks[k * (W + 1) + 16 * mb + ln % 16];
-      const double b = zs[(16 * nb + ln % 16) * (W + 1) + k];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      for (int mb = 0; mb < NB; ++mb) {
+        if (mb < mb0 || mb >= mb1) continue;
+        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < W / 4; ++kk) {
+          const int k = 4 * kk + ln / 16;
+          // A[m][k] = K[k][m], B[k][n] = Z[n][k]  ->  D[m][n] = (Z K)[n][m]
+          const double a = Ks[(c * W + k) * (W + 1) + 16 * mb + (ln & 15)];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, z[kk], acc, 0, 0, 0);
+        }
+        if (r < sg.n) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int m = 16 * mb + 4 * v + ln / 16;
+            if (m < Lc) outt[(c * S + r) * Lc + m] = static_cast<float>(acc[v]);
+          }
+        }
+      }
     }
-    if (r < F.rows) {
+    __syncthreads();
+    // contiguous runs of S x L_c floats per sub-cube, written in place into P
+    const int nfl = sg.n * Lc;
+    for (int c = 0; c < C; ++c) {
+      float *dst = A.p + c * g.p_sub + F.poff + (static_cast<int64_t>(sg.y) * F.hx + sg.s0) * Lc;
+      for (int e = threadIdx.x; e < nfl; e += blockDim.x) dst[e] = outt[c * S * Lc + e];
+    }
+  }
+  drain_loads();
+}
+
+// One sub-cube (C = 1): each wave keeps the K columns of its 16-channel output
+// block in registers, so LDS holds only the staging buffers and segments can
+// be long.  Wave w computes channel block w % NB of the row blocks
+// w / NB, w / NB + RW, ... (RW = 4 / NB waves share a block; for NB = 3 the
+// fourth wave idles).
+template <int NB>
+__global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
+  constexpr int W = NB * 16;
+  constexpr int RW = NB >= 4 ? 1 : 4 / NB;
+  constexpr int MAXRB = kMaxSeg / 16;  // row blocks per segment, upper bound
+  extern __shared__ float sm[];
+  __shared__ double dsh[2][kMaxSeg];
+  const NucGeom &g = A.g;
+  const int q = blockIdx.y, chunk = blockIdx.x;
+  const FacetView F = facet_view(g, q);
+  const int y0 = chunk * A.chunk_wrows;
+  if (y0 >= F.hy) return;
+  const int y1 = min(y0 + A.chunk_wrows, F.hy);
+  const int S = A.seg, L = g.L, Lc = g.Lc;
+  const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;
+  const int BUF = stage_words(S, L);
+  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const bool active = wave < NB * RW;
+  const int mb = wave % NB, rres = wave / NB;
+  const int nrb = S / 16;
+  double kr[W / 4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = 16 * mb + 4 * v + ln / 16;
-        if (j < A.g.Lc) A.p[F.poff + r * A.g.Lc + j] = static_cast<float>(acc[v]);
+  for (int kk = 0; kk < W / 4; ++kk)
+    kr[kk] = A.kmat[static_cast<int64_t>(q) * A.lc16 * A.lc16 + (4 * kk + ln / 16) * A.lc16 + 16 * mb + (ln & 15)];
+
+  issue_seg(A, F, seg_of(0, y0, nsx, S, F.hx), sm, dsh[0], true);
+  for (int i = 0; i < nseg; ++i) {
+    wait_loads_and_sync();
+    if (i + 1 < nseg) issue_seg(A, F, seg_of(i + 1, y0, nsx, S, F.hx), sm + ((i + 1) & 1) * BUF, dsh[(i + 1) & 1], true);
+    float *buf = sm + (i & 1) * BUF;
+    const double *d = dsh[i & 1];
+    const Seg sg = seg_of(i, y0, nsx, S, F.hx);
+    // results go straight from registers to P (rows of other segments are
+    // never touched), so the stores drain while later row blocks compute
+    float *dst = A.p + F.poff + (static_cast<int64_t>(sg.y) * F.hx + sg.s0) * Lc;
+#pragma unroll
+    for (int j = 0; j < MAXRB; ++j) {
+      const int nb = rres + j * RW;
+      if (active && nb < nrb) {
+        const int r = 16 * nb + (ln & 15);
+        // Z[r][k] = P[r][k] + D_r X[r][k] (one sub-cube: X and P rows have the
+        // same layout), read at compile-time offsets from per-row bases
+        const bool rv = r < sg.n;
+        const float *xr = buf + r * L + ln / 16, *pr = xr + S * L;
+        const double dr = d[r];
+        v4d res = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < W / 4; ++kk) {
+          // A[m][k] = K[k][m], B[k][n] = Z[n][k]  ->  D[m][n] = (Z K)[n][m]
+          const bool ok = rv && 4 * kk + ln / 16 < Lc;
+          const double z = ok ? fma(dr, static_cast<double>(xr[4 * kk]), static_cast<double>(pr[4 * kk])) : 0.0;
+          res = __builtin_amdgcn_mfma_f64_16x16x4f64(kr[kk], z, res, 0, 0, 0);
+        }
+        if (r < sg.n) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int m = 16 * mb + 4 * v + ln / 16;
+            if (m < Lc) dst[r * Lc + m] = static_cast<float>(res[v]);
+          }
+        }
       }
     }
   }
+  drain_loads();
 }
 
-// Thread = one pixel and up to 4 channels; all loads of the thread (up to 4
-// facets x 4 channels of P, and the previous gradient) are independent.
+// A workgroup owns a run of kGatherPx pixels of one image row.  Its first
+// threads resolve, once per pixel, the (at most four) covering facets: window
+// weight and the offset of the pixel's row in each facet's P (sub-cube 0).
+// Then thread t works on channel t % L of pixels t / L, t / L + 256 / L, ...:
+// every P read and the gradient update are coalesced across the channels.
+constexpr int kGatherPx = 64;
+
 __global__ void __launch_bounds__(256) nuc_gather_kernel(GatherArgs A) {
+  __shared__ double dk[kGatherPx][4];
+  __shared__ int64_t rk[kGatherPx][4];
   const NucGeom &g = A.g;
-  const int ngrp = (g.L + 3) / 4;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t npix = static_cast<int64_t>(g.ny) * g.nx;
-  const int64_t pix = t / ngrp;
-  if (pix >= npix) return;
-  const int ch0 = 4 * static_cast<int>(t - pix * ngrp);
-  const int y = static_cast<int>(pix / g.nx), x = static_cast<int>(pix - static_cast<int64_t>(y) * g.nx);
-  const int sy0 = static_cast<int>((static_cast<int64_t>(y + 1) * g.qy + g.ny - 1) / g.ny) - 1;
-  const int sx0 = static_cast<int>((static_cast<int64_t>(x + 1) * g.qx + g.nx - 1) / g.nx) - 1;
-  const int ncy = (sy0 + 1 < g.qy && y >= g.ty[sy0 + 1] - g.oy) ? 2 : 1;
-  const int ncx = (sx0 + 1 < g.qx && x >= g.tx[sx0 + 1] - g.ox) ? 2 : 1;
-  // the (at most four) covering facets of sub-cube 0: weight and P row offset
-  double dk[4];
-  int64_t rk[4];
+  const int y = blockIdx.y, x0 = blockIdx.x * kGatherPx;
+  const int npx = min(kGatherPx, g.nx - x0);
+  if (threadIdx.x < kGatherPx) {
+    const int i = threadIdx.x, x = x0 + i;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int dy = k >> 1, dx = k & 1;
-    dk[k] = 0.0;
-    rk[k] = 0;
-    if (dy < ncy && dx < ncx) {
-      const FacetView F = facet_view(g, (sy0 + dy) * g.qx + (sx0 + dx));
-      const int yy = y - F.wy0, xx = x - F.wx0;
-      dk[k] = ramp(yy, F.sy, g.qy, g.oy, F.hy) * ramp(xx, F.sx, g.qx, g.ox, F.hx);
-      rk[k] = F.poff + (static_cast<int64_t>(yy) * F.hx + xx) * g.Lc;
+    for (int k = 0; k < 4; ++k) {
+      dk[i][k] = 0.0;
+      rk[i][k] = 0;
+    }
+    if (i < npx) {
+      const int sy0 = static_cast<int>((static_cast<int64_t>(y + 1) * g.qy + g.ny - 1) / g.ny) - 1;
+      const int sx0 = static_cast<int>((static_cast<int64_t>(x + 1) * g.qx + g.nx - 1) / g.nx) - 1;
+      const int ncy = (sy0 + 1 < g.qy && y >= g.ty[sy0 + 1] - g.oy) ? 2 : 1;
+      const int ncx = (sx0 + 1 < g.qx && x >= g.tx[sx0 + 1] - g.ox) ? 2 : 1;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int dy = k >> 1, dx = k & 1;
+        if (dy < ncy && dx < ncx) {
+          const FacetView F = facet_view(g, (sy0 + dy) * g.qx + (sx0 + dx));
+          const int yy = y - F.wy0, xx = x - F.wx0;
+          dk[i][k] = ramp(yy, F.sy, g.qy, g.oy, F.hy) * ramp(xx, F.sx, g.qx, g.ox, F.hx);
+          rk[i][k] = F.poff + (static_cast<int64_t>(yy) * F.hx + xx) * g.Lc;
+        }
+      }
     }
   }
-  float pv[4][4], gv[4];
+  __syncthreads();
+  const int L = g.L, per = 256 / L;  // pixels per pass of the workgroup (L <= 256)
+  const int t = threadIdx.x;
+  if (t >= per * L) return;
+  const int ch = t % L, c = ch % g.C, l = ch / g.C;
+  const float *pc = A.p + c * g.p_sub + l;
+  for (int i = t / L; i < npx; i += per) {
+    float pv[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int ch = ch0 + e;
-    const bool ok = ch < g.L;
-    const int c = ch % g.C, l = ch / g.C;
+    for (int k = 0; k < 4; ++k) pv[k] = dk[i][k] != 0.0 ? pc[rk[i][k]] : 0.0f;
+    double sum = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pv[e][k] = (ok && dk[k] != 0.0) ? A.p[c * g.p_sub + rk[k] + l] : 0.0f;
-    gv[e] = (ok && A.beta != 0.0f) ? A.grad[pix * g.L + ch] : 0.0f;
-  }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int ch = ch0 + e;
-    if (ch < g.L) {
-      double sum = 0.0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) sum += dk[k] * static_cast<double>(pv[e][k]);
-      const float v = static_cast<float>(A.zeta * sum);
-      A.grad[pix * g.L + ch] = A.beta != 0.0f ? fmaf(A.beta, gv[e], v) : v;
-    }
+    for (int k = 0; k < 4; ++k) sum += dk[i][k] * static_cast<double>(pv[k]);
+    const float v = static_cast<float>(A.zeta * sum);
+    float *gp = A.grad + (static_cast<int64_t>(y) * g.nx + x0 + i) * L + ch;
+    *gp = A.beta != 0.0f ? fmaf(A.beta, *gp, v) : v;
   }
 }
 
@@ -386,16 +557,36 @@ static int check_launch(const char *what) {
   return FHS_OK;
 }
 
-int launch_nuc_gram(const NucArgs &a, int nfacets, void *stream) {
+// dynamic LDS bytes of the Gram / reconstruction kernels
+size_t nuc_lds_bytes(const NucArgs &a, bool recon) {
+  const int W = a.lc16;
+  // (+64 words: masked-out lanes read up to 63 words past a buffer)
+  const size_t stage = static_cast<size_t>(2 * 2 * a.seg * a.g.L + 64) * sizeof(float);
+  if (!recon) return stage > 8192 ? stage : 8192;  // the unit reduction reuses it (4 x 256 doubles)
+  return static_cast<size_t>(a.g.C) * W * (W + 1) * sizeof(double) + stage +
+         static_cast<size_t>(a.seg * a.g.L) * sizeof(float);
+}
+
+int launch_nuc_gram(const NucArgs &a, int nspatial, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const dim3 grid(a.chunks, nfacets);
+  const size_t lds = nuc_lds_bytes(a, false);
+#define FHS_GRAM_CASE(NB)                                                                               \
+  case NB: {                                                                                            \
+    constexpr int KM = gram_subcubes<NB>();                                                             \
+    if (a.g.C == 1 || KM == 1)                                                                          \
+      hipLaunchKernelGGL((nuc_gram_kernel<NB, 1>), dim3(a.chunks, nspatial, a.g.C), dim3(256), lds, s, a); \
+    else                                                                                                \
+      hipLaunchKernelGGL((nuc_gram_kernel<NB, KM>), dim3(a.chunks, nspatial, (a.g.C + KM - 1) / KM),     \
+                         dim3(256), lds, s, a);                                                         \
+  } break;
   switch (a.lc16 / 16) {
-    case 1: hipLaunchKernelGGL(nuc_gram_kernel<1>, grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(nuc_gram_kernel<2>, grid, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(nuc_gram_kernel<3>, grid, dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(nuc_gram_kernel<4>, grid, dim3(256), 0, s, a); break;
+    FHS_GRAM_CASE(1)
+    FHS_GRAM_CASE(2)
+    FHS_GRAM_CASE(3)
+    FHS_GRAM_CASE(4)
     default: return fail(FHS_EUNSUPPORTED, "more than 64 channels per sub-cube");
   }
+#undef FHS_GRAM_CASE
   return check_launch("nuc_gram");
 }
 
@@ -404,24 +595,37 @@ int launch_nuc_eig(const NucArgs &a, int nfacets, void *stream) {
   return check_launch("nuc_eig");
 }
 
-int launch_nuc_recon(const NucArgs &a, int nfacets, int rowblocks, void *stream) {
+int launch_nuc_recon(const NucArgs &a, int nspatial, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const dim3 grid(rowblocks, nfacets);
+  const dim3 grid(a.chunks, nspatial);
+  if (a.g.C == 1) {
+    // (+64 words: masked-out lanes read up to 63 words past a buffer)
+    const size_t lds1 = static_cast<size_t>(2 * 2 * a.seg * a.g.L + 64) * sizeof(float);
+    switch (a.lc16 / 16) {
+      case 1: hipLaunchKernelGGL(nuc_recon1_kernel<1>, grid, dim3(256), lds1, s, a); break;
+      case 2: hipLaunchKernelGGL(nuc_recon1_kernel<2>, grid, dim3(256), lds1, s, a); break;
+      case 3: hipLaunchKernelGGL(nuc_recon1_kernel<3>, grid, dim3(256), lds1, s, a); break;
+      case 4: hipLaunchKernelGGL(nuc_recon1_kernel<4>, grid, dim3(256), lds1, s, a); break;
+      default: return fail(FHS_EUNSUPPORTED, "more than 64 channels per sub-cube");
+    }
+    return check_launch("nuc_recon");
+  }
+  const size_t lds = nuc_lds_bytes(a, true);
+  if (lds > 160 * 1024) return fail(FHS_EUNSUPPORTED, "reconstruction tile exceeds the LDS");
   switch (a.lc16 / 16) {
-    case 1: hipLaunchKernelGGL(nuc_recon_kernel<1>, grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(nuc_recon_kernel<2>, grid, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(nuc_recon_kernel<3>, grid, dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(nuc_recon_kernel<4>, grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(nuc_recon_kernel<1>, grid, dim3(256), lds, s, a); break;
+    case 2: hipLaunchKernelGGL(nuc_recon_kernel<2>, grid, dim3(256), lds, s, a); break;
+    case 3: hipLaunchKernelGGL(nuc_recon_kernel<3>, grid, dim3(256), lds, s, a); break;
+    case 4: hipLaunchKernelGGL(nuc_recon_kernel<4>, grid, dim3(256), lds, s, a); break;
     default: return fail(FHS_EUNSUPPORTED, "more than 64 channels per sub-cube");
   }
   return check_launch("nuc_recon");
 }
 
 int launch_nuc_gather(const GatherArgs &a, void *stream) {
-  const int64_t total = static_cast<int64_t>(a.g.ny) * a.g.nx * ((a.g.L + 3) / 4);
-  const int64_t blocks = (total + 255) / 256;
-  hipLaunchKernelGGL(nuc_gather_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), a);
+  if (a.g.L > 256) return fail(FHS_EUNSUPPORTED, "gather: more than 256 channels");
+  const dim3 grid((a.g.nx + kGatherPx - 1) / kGatherPx, a.g.ny);
+  hipLaunchKernelGGL(nuc_gather_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), a);
   return check_launch("nuc_gather");
 }
 

@@ -13,6 +13,8 @@
 #include <new>
 #include <string>
 
+#include <hip/hip_runtime.h>
+
 #include "fhs_internal.h"
 
 namespace fhs {
@@ -28,6 +30,14 @@ int fail(int code, const std::string &msg) {
 
 static int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
+}  // namespace fhs
+
+namespace fhs {
+int64_t nuc_recon_lds(const fhs_plan *p, int S) {
+  const int64_t W = p->lc16;
+  if (p->C == 1) return (4 * static_cast<int64_t>(S) * p->L + 64) * 4;  // K held in registers
+  return static_cast<int64_t>(p->C) * W * (W + 1) * 8 + 5 * static_cast<int64_t>(S) * p->L * 4;
+}
 }  // namespace fhs
 
 using namespace fhs;
@@ -179,8 +189,27 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
         ws = align256(ws + static_cast<int64_t>(p->Ky[b][j]) * p->Kx[b][j] * p->L * 4);
       }
     }
-  p->gram_chunk_rows = 4096;
-  p->gram_chunks = (p->max_rows + p->gram_chunk_rows - 1) / p->gram_chunk_rows;
+  // nuclear kernels: segments of S pixels of one window row, chunks of whole
+  // window rows of about 4096 pixels per workgroup
+  for (const auto &f : p->facets) {
+    p->max_hx = std::max(p->max_hx, f.wx1 - f.wx0);
+    p->max_hy = std::max(p->max_hy, f.wy1 - f.wy0);
+  }
+  {
+    fhs_tuning &t = p->tune;
+    for (int j = 0; j < kMaxLevels; ++j) t.ana_rows[j] = 64;
+    t.ana_phase = 4;
+    t.syn_rows = 64;
+    t.fin_rows = 128;
+    // largest S (at most 64 / 32 / 16 by channel count) whose reconstruction
+    // tile fits in 64 KB of LDS
+    t.nuc_seg = 64;
+    while (t.nuc_seg > 16 && nuc_recon_lds(p, t.nuc_seg) > 65536) t.nuc_seg /= 2;
+    t.nuc_chunk_rows = std::max(1, 4096 / p->max_hx);
+    t.concurrent = 1;
+    p->nuc_chunk_min = std::max(1, t.nuc_chunk_rows / 2);
+    p->gram_chunks = (p->max_hy + p->nuc_chunk_min - 1) / p->nuc_chunk_min;
+  }
   const int64_t nf = static_cast<int64_t>(p->facets.size());
   p->ws_gram = ws;
   ws = align256(ws + nf * p->gram_chunks * p->lc16 * p->lc16 * 8);
@@ -208,6 +237,12 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
 void fhs_plan_destroy(fhs_plan *plan) {
   if (!plan) return;
   if (!plan->prof_events.empty()) prof_release(plan);
+  if (plan->side) {
+    (void)hipStreamSynchronize(static_cast<hipStream_t>(plan->side));
+    (void)hipStreamDestroy(static_cast<hipStream_t>(plan->side));
+    (void)hipEventDestroy(static_cast<hipEvent_t>(plan->ev_fork));
+    (void)hipEventDestroy(static_cast<hipEvent_t>(plan->ev_join));
+  }
   delete plan;
 }
 
@@ -261,6 +296,31 @@ int fhs_plan_heuristics(const fhs_plan *p, const double *sigma_bar, double *mu, 
   return FHS_OK;
 }
 
+int fhs_plan_get_tuning(const fhs_plan *p, fhs_tuning *out) {
+  if (!p || !out) return fail(FHS_EINVAL, "fhs_plan_get_tuning: null argument");
+  *out = p->tune;
+  return FHS_OK;
+}
+
+int fhs_plan_set_tuning(fhs_plan *p, const fhs_tuning *t) {
+  if (!p || !t) return fail(FHS_EINVAL, "fhs_plan_set_tuning: null argument");
+  for (int j = 0; j < kMaxLevels; ++j)
+    if (t->ana_rows[j] < 8 || t->ana_rows[j] > 256 || t->ana_rows[j] % 8)
+      return fail(FHS_EINVAL, "ana_rows must be multiples of 8 in 8..256");
+  if (t->ana_phase != 1 && t->ana_phase != 2 && t->ana_phase != 4) return fail(FHS_EINVAL, "ana_phase must be 1, 2 or 4");
+  if (t->syn_rows < 16 || t->syn_rows > 256 || t->syn_rows % 8)
+    return fail(FHS_EINVAL, "syn_rows must be a multiple of 8 in 16..256");
+  if (t->fin_rows < 16 || t->fin_rows > 512 || t->fin_rows % 8)
+    return fail(FHS_EINVAL, "fin_rows must be a multiple of 8 in 16..512");
+  if (t->nuc_seg != 16 && t->nuc_seg != 32 && t->nuc_seg != 64) return fail(FHS_EINVAL, "nuc_seg must be 16, 32 or 64");
+  if (nuc_recon_lds(p, t->nuc_seg) > 160 * 1024) return fail(FHS_EINVAL, "nuc_seg: reconstruction tile exceeds the LDS");
+  if (t->nuc_chunk_rows < p->nuc_chunk_min)
+    return fail(FHS_EINVAL, "nuc_chunk_rows below the workspace's minimum (" + std::to_string(p->nuc_chunk_min) + ")");
+  if (t->concurrent != 0 && t->concurrent != 1) return fail(FHS_EINVAL, "concurrent must be 0 or 1");
+  p->tune = *t;
+  return FHS_OK;
+}
+
 int fhs_plan_set_workspace(fhs_plan *p, void *dev_ptr, int64_t bytes) {
   if (!p) return fail(FHS_EINVAL, "fhs_plan_set_workspace: null plan");
   if (!dev_ptr || bytes < p->ws_bytes)
@@ -268,6 +328,23 @@ int fhs_plan_set_workspace(fhs_plan *p, void *dev_ptr, int64_t bytes) {
   if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0) return fail(FHS_EINVAL, "workspace must be 256-byte aligned");
   p->ws = dev_ptr;
   p->ws_given = bytes;
+  if (!p->side) {
+    // side stream (default priority) and fork / join events for the
+    // concurrent nuclear chain; without them the step runs on one stream
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&a, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&b, hipEventDisableTiming) == hipSuccess) {
+      p->side = s;
+      p->ev_fork = a;
+      p->ev_join = b;
+    } else {
+      if (s) (void)hipStreamDestroy(s);
+      if (a) (void)hipEventDestroy(a);
+      (void)hipGetLastError();
+    }
+  }
   return FHS_OK;
 }
 

@@ -25,7 +25,7 @@ def declared_symbols():
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(fhs.library_path())
     names = declared_symbols()
-    assert len(names) == 24
+    assert len(names) == 27
     for n in names:
         assert hasattr(lib, n), n
     # and the binding declares a signature for each of them
@@ -110,3 +110,18 @@ def test_compute_without_workspace_is_an_error():
     assert b"workspace" in lib.fhs_last_error()
     rc = lib.fhs_plan_set_workspace(p._p, ctypes.c_void_p(0), 0)
     assert rc == -1
+
+
+def test_tuning_roundtrip_and_validation():
+    plan = fhs.Plan(256, 256, 20, 2, 2, 1, 32, 32, 4)
+    t = plan.tuning
+    assert t["ana_rows"][:4] == [64, 64, 64, 64] and t["concurrent"] == 1
+    assert t["nuc_seg"] in (16, 32, 64)
+    plan.tuning = {"ana_rows": [32, 64, 128, 16, 64, 64], "fin_rows": 256, "nuc_seg": 16}
+    t2 = plan.tuning
+    assert t2["ana_rows"][:4] == [32, 64, 128, 16] and t2["fin_rows"] == 256 and t2["nuc_seg"] == 16
+    for bad in ({"ana_rows": [12, 64, 64, 64, 64, 64]}, {"ana_phase": 3}, {"syn_rows": 20}, {"nuc_seg": 48},
+                {"nuc_chunk_rows": 0}, {"concurrent": 2}):
+        with pytest.raises(fhs.FhsError):
+            plan.tuning = bad
+    assert plan.tuning == t2   # a rejected setting leaves the plan unchanged

@@ -178,3 +178,30 @@ def test_facet_prox_step_cfg2_full():
     check("P+", gp, np.concatenate([q.reshape(-1) for row in Pn for q in row]))
     check("W+", gw, np.concatenate(Wn, axis=1).reshape(-1))
     check("G", gg, G.reshape(-1))
+
+
+def test_autotune_keeps_results():
+    """Launch shapes chosen by the autotuner change speed only: the tuned step
+    matches the oracle and the default-shape step."""
+    pb, plan = make("cfg1_256x256x20_q2x2_o32", warm=True)
+    args = [dev(pb.theta_flat()), dev(pb.theta_bar_flat()), dev(pb.mu), dev(pb.mu_bar_flat())]
+    x = dev(pb.X)
+
+    def step():
+        p, w = dev(pb.P_flat()), dev(pb.W_flat())
+        g = torch.empty(plan.sizes["n_x"], device="cuda")
+        plan.facet_prox_step(x, p, w, args[0], args[1], args[2], args[3], 1.0, 1.0, g)
+        return host(p), host(w), host(g)
+
+    ref = step()
+    t0 = plan.tuning
+    scratch = [dev(pb.P_flat()), dev(pb.W_flat()), torch.empty(plan.sizes["n_x"], device="cuda")]
+    t1 = plan.autotune(x, scratch[0], scratch[1], *args, scratch[2], reps=1)
+    log(f"    default {t0}\n    tuned   {t1}")
+    got = step()
+    for name, a, b in zip(("P+", "W+", "G"), got, ref):
+        check(name + " (tuned vs default)", a, b, tol=1e-6)
+    Pn, Wn, G = pb.oracle_step()
+    check("P+", got[0], np.concatenate([q.reshape(-1) for row in Pn for q in row]))
+    check("W+", got[1], np.concatenate(Wn, axis=1).reshape(-1))
+    check("G", got[2], G.reshape(-1))
