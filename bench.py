@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default launch shapes")
+    ap.add_argument("--tuning", default=None, metavar="JSON",
+                    help="fixed launch shapes (a JSON object as printed in the 'tuning' field) instead of autotuning")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (the reference "
                          "dispatch that scales HBM counters read under rocprofv3 --pmc)")
@@ -168,7 +170,10 @@ def main():
         log(f"[bench] calibration copy kernel: {n * 4} bytes read, {n * 4} bytes written")
         del src, dst
 
-    if not args.no_autotune:
+    if args.tuning:
+        plan.tuning = json.loads(args.tuning)
+        log(f"[bench] fixed tuning {plan.tuning}")
+    elif not args.no_autotune:
         # launch shapes picked on the workload itself (outside the timed region);
         # the duals it scribbles on are reset afterwards
         t0a = time.perf_counter()
