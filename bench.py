@@ -123,6 +123,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default launch shapes")
+    ap.add_argument("--form", choices=("batched", "plain"), default="batched",
+                    help="batched: every operator one launch over all facets (default); plain: the "
+                         "per-facet execution form, one launch per facet and operator")
     ap.add_argument("--tuning", default=None, metavar="JSON",
                     help="fixed launch shapes (a JSON object as printed in the 'tuning' field) instead of autotuning")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -157,8 +160,10 @@ def main():
     g_d = torch.empty(s["n_x"], dtype=torch.float32, device="cuda")
     del X
 
+    plain = args.form == "plain"
+
     def one_step():
-        plan.facet_prox_step(x_d, p_d, w_d, th_d, tb_d, mu_d, mub_d, 1.0, 1.0, g_d)
+        plan.facet_prox_step(x_d, p_d, w_d, th_d, tb_d, mu_d, mub_d, 1.0, 1.0, g_d, plain=plain)
 
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
@@ -173,7 +178,7 @@ def main():
     if args.tuning:
         plan.tuning = json.loads(args.tuning)
         log(f"[bench] fixed tuning {plan.tuning}")
-    elif not args.no_autotune:
+    elif not args.no_autotune and not plain:
         # launch shapes picked on the workload itself (outside the timed region);
         # the duals it scribbles on are reset afterwards
         t0a = time.perf_counter()
@@ -224,7 +229,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (nuclear path f64-accumulated)",
         "data": "synthetic (seeded Gaussian-blob cube with power-law spectra)",
-        "config": {"workload": w.name, "ny": w.ny, "nx": w.nx, "channels": w.L, "facets": [w.qy, w.qx],
+        "config": {"workload": w.name, "form": args.form, "ny": w.ny, "nx": w.nx, "channels": w.L,
+                   "facets": [w.qy, w.qx],
                    "overlap_px": w.overlap, "subcubes": w.C, "levels": w.levels, "bases": "db1-db8+dirac",
                    "parallelism": "single GPU"},
         "roofline": {"kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

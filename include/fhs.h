@@ -206,6 +206,19 @@ int fhs_facet_prox_step(const fhs_plan *plan, const float *xcheck, float *p_inou
                         const double *mu, const double *mu_bar, double zeta, double kappa,
                         float *grad, void *stream);
 
+/* The same step in the per-facet execution form (the paper's organisation:
+ * one facet at a time, Sec. 2.4 and Fig. 4): every operator is launched once
+ * per spatial facet on the coefficients / pixels / window rows that facet
+ * owns, in raster order (analysis level by level, synthesis coarse to fine,
+ * the nuclear update facet by facet, then the gather tile by tile), on
+ * `stream` only.  Same arguments and the same results as fhs_facet_prox_step
+ * (bitwise for the wavelet part); kept as the baseline the batched form is
+ * measured against. */
+int fhs_facet_prox_step_plain(const fhs_plan *plan, const float *xcheck, float *p_inout,
+                              float *w_inout, const float *theta, const double *theta_bar,
+                              const double *mu, const double *mu_bar, double zeta, double kappa,
+                              float *grad, void *stream);
+
 /* Reweighting weights from the previous iterate X^(t) (Alg. 1,
  * weight updates):
  *   theta_bar_{f,j} = upsilon_bar_f / (s_j(D_q S~_q X_c) + upsilon_bar_f)  (eq. facet_hypersara_rank)

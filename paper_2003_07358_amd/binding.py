@@ -69,6 +69,10 @@ SYMBOLS = {
     "fhs_facet_prox_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_facet_prox_step_plain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "fhs_reweight": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fhs_pdfb_closure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -282,11 +286,13 @@ class Plan:
             self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"), float(zeta),
             self._t(grad, s["n_x"], torch.float32, "grad"), float(beta), _stream(xcheck)))
 
-    def facet_prox_step(self, xcheck, p, w, theta, theta_bar, mu, mu_bar, zeta, kappa, grad):
+    def facet_prox_step(self, xcheck, p, w, theta, theta_bar, mu, mu_bar, zeta, kappa, grad, plain=False):
+        """plain=True: the per-facet execution form (fhs_facet_prox_step_plain)."""
         import torch
         self._need_ws()
         s = self.sizes
-        _check(self._lib.fhs_facet_prox_step(
+        fn = self._lib.fhs_facet_prox_step_plain if plain else self._lib.fhs_facet_prox_step
+        _check(fn(
             self._p, self._t(xcheck, s["n_x"], torch.float32, "xcheck"),
             self._t(p, s["n_p"], torch.float32, "p"), self._t(w, s["n_w"], torch.float32, "w"),
             self._t(theta, s["n_theta"], torch.float32, "theta"),

@@ -55,13 +55,18 @@ int ana_lds_buf(const AnaArgs &a, int P) {
 }
 
 // mode 0: w = Psi^dagger x ; mode 1: l21 dual update of w ; mode 2: theta weights
+// Facet (fy, fx) >= 0 restricts every band to the coefficients that facet
+// owns (and the Dirac band to its tile), level >= 0 to one level: the
+// per-facet execution form.
 int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, const double *mu, double inv_kappa,
-                 int mode, void *stream) {
+                 int mode, void *stream, int fy = -1, int fx = -1, int level = -1) {
   int tkx1, nth;
   if (int rc = thread_cfg(p, &tkx1, &nth, kAnaThreads)) return rc;
   const int TKX = tkx1;
   const int levels = p->cfg.levels;
+  const bool facet = fy >= 0;
   for (int j = 0; j < levels; ++j) {
+    if (level >= 0 && j != level) continue;
     AnaArgs a;
     std::memset(&a, 0, sizeof(a));
     a.w = w;
@@ -101,8 +106,12 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       B.ll_out = j < levels - 1 ? ws_f(p, p->ws_ll[b][j]) : nullptr;
       B.Ky = p->Ky[b][j];
       B.Kx = p->Kx[b][j];
-      B.strips = ceil_div(B.Kx, TKX);
-      B.yblocks = ceil_div(B.Ky, a.tky);
+      B.ky_begin = facet ? p->own_y[b][j][fy] : 0;
+      B.ky_end = facet ? p->own_y[b][j][fy + 1] : B.Ky;
+      B.kx_begin = facet ? p->own_x[b][j][fx] : 0;
+      B.kx_end = facet ? p->own_x[b][j][fx + 1] : B.Kx;
+      B.strips = std::max(0, ceil_div(B.kx_end - B.kx_begin, TKX));
+      B.yblocks = std::max(0, ceil_div(B.ky_end - B.ky_begin, a.tky));
       B.ntap = p->ntap[b];
       for (int s = 0; s < 3; ++s) B.off[s] = coef_off(p, b, j, s);
       B.off[3] = j == levels - 1 ? ll_off(p, b) : -1;
@@ -117,9 +126,13 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       D.in_ny = p->cfg.ny;
       D.in_nx = p->cfg.nx;
       D.off[0] = dirac_off(p);
+      D.ky_begin = facet ? p->ty[fy] : 0;
+      D.ky_end = facet ? p->ty[fy + 1] : p->cfg.ny;
+      D.kx_begin = facet ? p->tx[fx] : 0;
+      D.kx_end = facet ? p->tx[fx + 1] : p->cfg.nx;
       // grid-stride workgroups for the Dirac band (kDiracE pixels in flight per thread)
-      D.strips = std::max(1, std::min(kMaxDiracWg, ceil_div(static_cast<int64_t>(p->cfg.ny) * p->cfg.nx,
-                                                            static_cast<int64_t>(kDiracE) * TKX)));
+      const int64_t npix = static_cast<int64_t>(D.ky_end - D.ky_begin) * (D.kx_end - D.kx_begin);
+      D.strips = std::max(1, std::min(kMaxDiracWg, ceil_div(npix, static_cast<int64_t>(kDiracE) * TKX)));
     }
     const int kid = j == 0 ? FHS_K_ANALYSIS_L1 : FHS_K_ANALYSIS;
     prof_begin(p, kid, stream);
@@ -130,12 +143,20 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
   return FHS_OK;
 }
 
-// x = beta x + alpha Psi w
-int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, float beta, void *stream) {
+// coefficient columns (strips of tk) covering output samples [b, e)
+int syn_strips(int b, int e, int tk) { return e > b ? ceil_div((e - 1) / 2 - b / 2 + 1, tk) : 0; }
+
+// x = beta x + alpha Psi w.  Facet (fy, fx) >= 0 restricts the outputs to the
+// samples that facet owns, level >= 0 to one level (0 = the final level-1
+// pass): the per-facet execution form.
+int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, float beta, void *stream, int fy = -1,
+                  int fx = -1, int level = -1) {
   int tk, nth;
   if (int rc = thread_cfg(p, &tk, &nth)) return rc;
   const int L = p->L, levels = p->cfg.levels;
+  const bool facet = fy >= 0;
   for (int j = levels - 1; j >= 1; --j) {  // 0-based level j -> writes low-low band of level j-1
+    if (level >= 0 && j != level) continue;
     SynArgs s;
     std::memset(&s, 0, sizeof(s));
     s.L = L;
@@ -156,18 +177,24 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
       B.Kx = p->Kx[b][j];
       B.ny = p->in_ny[b][j];
       B.nx = p->in_nx[b][j];
-      B.strips = ceil_div((B.nx + 1) / 2, tk);
-      B.yblocks = ceil_div(B.ny, s.ty);
+      B.y_begin = facet ? p->own_y[b][j - 1][fy] : 0;
+      B.y_end = facet ? p->own_y[b][j - 1][fy + 1] : B.ny;
+      B.x_begin = facet ? p->own_x[b][j - 1][fx] : 0;
+      B.x_end = facet ? p->own_x[b][j - 1][fx + 1] : B.nx;
+      B.strips = syn_strips(B.x_begin, B.x_end, tk);
+      B.yblocks = std::max(0, ceil_div(B.y_end - B.y_begin, s.ty));
       B.ntap = p->ntap[b];
       s.wg_prefix[b] = prefix;
       prefix += B.strips * B.yblocks;
     }
     s.wg_prefix[kBases] = prefix;
+    if (prefix == 0) continue;
     prof_begin(p, FHS_K_SYNTHESIS, stream);
     const int rc = launch_synthesis(s, nth, stream);
     prof_end(p, FHS_K_SYNTHESIS, stream);
     if (rc) return rc;
   }
+  if (level > 0) return FHS_OK;
   SynFinalArgs f;
   std::memset(&f, 0, sizeof(f));
   for (int b = 0; b < kBases; ++b) {
@@ -194,8 +221,12 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
   f.Lc = p->Lc;
   f.tk = tk;
   f.ty = p->tune.fin_rows;
-  f.strips = ceil_div((p->cfg.nx + 1) / 2, tk);
-  f.yblocks = ceil_div(p->cfg.ny, f.ty);
+  f.y_begin = facet ? p->ty[fy] : 0;
+  f.y_end = facet ? p->ty[fy + 1] : p->cfg.ny;
+  f.x_begin = facet ? p->tx[fx] : 0;
+  f.x_end = facet ? p->tx[fx + 1] : p->cfg.nx;
+  f.strips = syn_strips(f.x_begin, f.x_end, tk);
+  f.yblocks = ceil_div(f.y_end - f.y_begin, f.ty);
   for (int grp = 0; grp < 2; ++grp) {
     const int kid = grp == 0 ? FHS_K_SYNTH_FINAL_A : FHS_K_SYNTH_FINAL_B;
     prof_begin(p, kid, stream);
@@ -232,12 +263,15 @@ void fill_geom(const fhs_plan *p, NucGeom &g) {
   g.p_sub = p->p_sub;
 }
 
-int run_gather(const fhs_plan *p, const float *pdual, float *grad, double zeta, float beta, void *stream);
+int run_gather(const fhs_plan *p, const float *pdual, float *grad, double zeta, float beta, void *stream,
+               int fy = -1, int fx = -1);
 
 // mode 0: dual update of p (+ gather unless no_gather); mode 1: weights only
+// q >= 0: only spatial facet q (all its sub-cubes), without the gather: the
+// per-facet execution form.
 int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *theta_bar, const double *mu_bar,
                 double zeta, double *theta_bar_out, float *grad, float beta, int mode, void *stream,
-                bool no_gather = false) {
+                bool no_gather = false, int q = -1) {
   NucArgs a;
   std::memset(&a, 0, sizeof(a));
   fill_geom(p, a.g);
@@ -255,10 +289,13 @@ int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *t
   a.seg = p->tune.nuc_seg;
   a.lc16 = p->lc16;
   a.mode = mode;
-  const int nf = static_cast<int>(p->facets.size());
+  a.q0 = q >= 0 ? q : 0;
+  a.eig_q = q;
+  const int nspatial = q >= 0 ? 1 : p->Q;
+  const int nf = q >= 0 ? p->C : static_cast<int>(p->facets.size());
   int rc;
   prof_begin(p, FHS_K_NUC_GRAM, stream);
-  rc = launch_nuc_gram(a, p->Q, stream);
+  rc = launch_nuc_gram(a, nspatial, stream);
   prof_end(p, FHS_K_NUC_GRAM, stream);
   if (rc) return rc;
   prof_begin(p, FHS_K_NUC_EIG, stream);
@@ -267,17 +304,23 @@ int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *t
   if (rc) return rc;
   if (mode == 1) return FHS_OK;
   prof_begin(p, FHS_K_NUC_RECON, stream);
-  rc = launch_nuc_recon(a, p->Q, stream);
+  rc = launch_nuc_recon(a, nspatial, stream);
   prof_end(p, FHS_K_NUC_RECON, stream);
   if (rc) return rc;
-  if (no_gather) return FHS_OK;
+  if (no_gather || q >= 0) return FHS_OK;
   return run_gather(p, pdual, grad, zeta, beta, stream);
 }
 
-int run_gather(const fhs_plan *p, const float *pdual, float *grad, double zeta, float beta, void *stream) {
+// fy >= 0: only the tile of facet (fy, fx).
+int run_gather(const fhs_plan *p, const float *pdual, float *grad, double zeta, float beta, void *stream, int fy,
+               int fx) {
   GatherArgs ga;
   std::memset(&ga, 0, sizeof(ga));
   fill_geom(p, ga.g);
+  ga.y_begin = fy >= 0 ? p->ty[fy] : 0;
+  ga.y_end = fy >= 0 ? p->ty[fy + 1] : p->cfg.ny;
+  ga.x_begin = fy >= 0 ? p->tx[fx] : 0;
+  ga.x_end = fy >= 0 ? p->tx[fx + 1] : p->cfg.nx;
   ga.p = pdual;
   ga.grad = grad;
   ga.zeta = zeta;
@@ -346,6 +389,37 @@ int fhs_facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, fl
     return rc ? rc : fail(FHS_EHIP, "join of the side stream failed");
   if (rc) return rc;
   return run_gather(p, pdual, grad, zeta, 1.0f, stream);
+}
+
+int fhs_facet_prox_step_plain(const fhs_plan *p, const float *xcheck, float *pdual, float *w, const float *theta,
+                              const double *theta_bar, const double *mu, const double *mu_bar, double zeta,
+                              double kappa, float *grad, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!xcheck || !pdual || !w || !theta || !theta_bar || !mu || !mu_bar || !grad)
+    return fail(FHS_EINVAL, "fhs_facet_prox_step_plain: null array");
+  if (!(zeta > 0) || !(kappa > 0)) return fail(FHS_EINVAL, "zeta and kappa must be positive");
+  const int qy = p->cfg.qy, qx = p->cfg.qx, levels = p->cfg.levels;
+  // l21: analysis level by level, facet by facet in raster order (a facet's
+  // window needs the low-low band its top / left neighbours own)
+  for (int j = 0; j < levels; ++j)
+    for (int sy = 0; sy < qy; ++sy)
+      for (int sx = 0; sx < qx; ++sx)
+        if (int rc = run_analysis(p, xcheck, w, const_cast<float *>(theta), mu, 1.0 / kappa, 1, stream, sy, sx, j))
+          return rc;
+  // synthesis coarse to fine, each facet writing the samples it owns
+  for (int j = levels - 1; j >= 0; --j)
+    for (int sy = 0; sy < qy; ++sy)
+      for (int sx = 0; sx < qx; ++sx)
+        if (int rc = run_synthesis(p, w, grad, static_cast<float>(kappa), 0.0f, stream, sy, sx, j)) return rc;
+  // nuclear: facet by facet (all sub-cubes of a spatial facet together), then
+  // the gather tile by tile
+  for (int q = 0; q < p->Q; ++q)
+    if (int rc = run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, stream, true, q))
+      return rc;
+  for (int sy = 0; sy < qy; ++sy)
+    for (int sx = 0; sx < qx; ++sx)
+      if (int rc = run_gather(p, pdual, grad, zeta, 1.0f, stream, sy, sx)) return rc;
+  return FHS_OK;
 }
 
 int fhs_reweight(const fhs_plan *p, const float *x, const double *upsilon, const double *upsilon_bar, float *theta,

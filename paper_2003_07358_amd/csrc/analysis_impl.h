@@ -70,10 +70,10 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
   const int chan = lv ? (B.in_natural ? c + lane * C : p) : 0;
   const int TKX = A.tkx1;
   const int strip = tile % B.strips, yb = tile / B.strips;
-  const int kx0 = strip * TKX, ky0 = yb * A.tky;
-  const int ky1 = min(ky0 + A.tky, B.Ky);
+  const int kx0 = B.kx_begin + strip * TKX, ky0 = B.ky_begin + yb * A.tky;
+  const int ky1 = min(ky0 + A.tky, B.ky_end);
   const int kx = kx0 + kq;
-  const bool ok = lv && kx < B.Kx;
+  const bool ok = lv && kx < B.kx_end;
   const int NC = 2 * TKX + NTAP - 2;        // input columns of a row segment
   const int ROW = A.lds_row;                // LDS words per staged input row
   const int col0 = 2 * kx0 + 2 - NTAP;      // first input column
@@ -96,7 +96,7 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int i = 64 * j + ln, cc = i / TKX, kk = i - cc * TKX;
-    th_voff[j] = (cc < C && kx0 + kk < B.Kx) ? static_cast<int>((static_cast<int64_t>(cc) * A.I + kx0 + kk) * 4)
+    th_voff[j] = (cc < C && kx0 + kk < B.kx_end) ? static_cast<int>((static_cast<int64_t>(cc) * A.I + kx0 + kk) * 4)
                                              : static_cast<int>(0x80000000u);
   }
   const int nth_chunks = (C * TKX + 63) / 64;
@@ -119,7 +119,7 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
         if (g >= nsteps || ky < 0 || ky >= B.Ky || boff < 0) continue;
         const int64_t rowi = boff + static_cast<int64_t>(ky) * B.Kx + kx0;  // first coefficient row
         // W of the TKX coefficient rows: TKX * L contiguous floats
-        const int nw = min(TKX, B.Kx - kx0) * L;
+        const int nw = min(TKX, B.kx_end - kx0) * L;
         const fhs_int32x4 wr = buffer_rsrc(A.w + rowi * L, static_cast<unsigned>(nw * 4));
         float *wdst = buf + A.lds_wv + (4 * k + s) * A.wpad;
         for (int j = 0; j < A.wpad; j += 64)
@@ -229,17 +229,27 @@ __device__ __forceinline__ void dirac(const AnaArgs &A, const AnaBand &B, int wg
   const int p = c * Lc + lane;
   const int chan = lv ? c + lane * C : 0;
   constexpr int E = 4;
-  const int64_t npix = static_cast<int64_t>(B.in_ny) * B.in_nx;
+  // pixels of the rectangle [ky_begin, ky_end) x [kx_begin, kx_end), row-major
+  const int rw = B.kx_end - B.kx_begin;
+  const bool full = rw == B.in_nx;
+  const int64_t npix = static_cast<int64_t>(B.ky_end - B.ky_begin) * rw;
+  const int64_t pix_first = static_cast<int64_t>(B.ky_begin) * B.in_nx + B.kx_begin;
   const int64_t stride = static_cast<int64_t>(B.strips) * A.tkx1;  // strips = Dirac workgroups
   float thr = 0.0f;
   if (MODE == 1) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
   if (MODE == 2) thr = static_cast<float>(A.mu[c]);
   for (int64_t pix0 = static_cast<int64_t>(wg) * A.tkx1 + kq; pix0 - kq < npix; pix0 += E * stride) {
     float v[E], w[E], th[E];
+    int64_t pixe[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int64_t pix = pix0 + e * stride;
-      const bool ok = lv && pix < npix;
+      const int64_t li = pix0 + e * stride;
+      pixe[e] = full ? pix_first + li : pix_first + (li / rw) * B.in_nx + li % rw;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const bool ok = lv && pix0 + e * stride < npix;
+      const int64_t pix = pixe[e];
       const int64_t i = B.off[0] + pix;
       v[e] = ok ? B.in[pix * L + chan] * (1.0f / 3.0f) : 0.0f;
       w[e] = (ok && MODE == 1) ? A.w[i * L + p] : 0.0f;
@@ -247,9 +257,8 @@ __device__ __forceinline__ void dirac(const AnaArgs &A, const AnaBand &B, int wg
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int64_t pix = pix0 + e * stride;
-      const bool ok = lv && pix < npix;
-      const int64_t i = B.off[0] + pix;
+      const bool ok = lv && pix0 + e * stride < npix;
+      const int64_t i = B.off[0] + pixe[e];
       if (MODE == 0) {
         if (ok) A.w[i * L + p] = v[e];
       } else if (MODE == 1) {

@@ -39,6 +39,8 @@ struct AnaBand {
   int strips, yblocks;
   int ntap;
   int64_t off[4];      // first coefficient row of lh, hl, hh, ll (ll: last level, else -1)
+  int ky_begin, ky_end, kx_begin, kx_end;  // coefficients computed (the whole band unless per facet);
+                                            // for the Dirac band: the pixel rectangle
 };
 
 struct AnaArgs {
@@ -70,6 +72,7 @@ struct SynBand {
   int Ky, Kx, ny, nx;
   int strips, yblocks;
   int ntap;
+  int y_begin, y_end, x_begin, x_end;  // output samples computed (all unless per facet)
 };
 
 struct SynArgs {
@@ -86,6 +89,7 @@ struct SynFinalArgs {
   float *x;                   // [ny][nx][L] natural channel order
   float alpha, beta;
   int ny, nx, L, Lcp, C, Lc, tk, ty, strips, yblocks;
+  int y_begin, y_end, x_begin, x_end;  // output pixels computed (all unless per facet)
 };
 
 // Facet geometry for the nuclear kernels (Sec. 2.4.2).
@@ -112,6 +116,8 @@ struct NucArgs {
   int seg;                   // pixels per staged segment
   int lc16;                  // Lc rounded up to 16
   int mode;                  // 0: dual update; 1: weights only
+  int q0;                    // first spatial facet of the launch (blockIdx.y offset)
+  int eig_q;                 // -1: eig over all C*Q facets; else facets c*Q + eig_q, c < C
 };
 
 struct GatherArgs {
@@ -120,6 +126,7 @@ struct GatherArgs {
   float *grad;
   double zeta;
   float beta;
+  int y_begin, y_end, x_begin, x_end;  // pixels updated (the image unless per facet)
 };
 
 // Data-fidelity dual (identity operator), primal update and relative variation.
@@ -168,6 +175,9 @@ struct fhs_plan {
   int in_ny[fhs::kBases][fhs::kMaxLevels], in_nx[fhs::kBases][fhs::kMaxLevels];
   int Ky[fhs::kBases][fhs::kMaxLevels], Kx[fhs::kBases][fhs::kMaxLevels];
   int64_t band_first[fhs::kBases];         // index into `bands` of the basis' first band
+  // per basis and level, the Q_axis + 1 boundaries of the coefficients each
+  // facet owns (used by the per-facet execution form)
+  std::vector<int> own_y[fhs::kBases][fhs::kMaxLevels], own_x[fhs::kBases][fhs::kMaxLevels];
   float h[fhs::kBases][fhs::kMaxTap], g[fhs::kBases][fhs::kMaxTap];
   int ntap[fhs::kBases];
   // workspace layout (bytes)

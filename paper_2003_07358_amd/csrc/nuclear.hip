@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
   extern __shared__ float sm[];
   __shared__ double dsh[2][kMaxSeg];
   const NucGeom &g = A.g;
-  const int q = blockIdx.y, chunk = blockIdx.x, Q = g.qy * g.qx;
+  const int q = A.q0 + blockIdx.y, chunk = blockIdx.x, Q = g.qy * g.qx;
   const FacetView F = facet_view(g, q);
   const int y0 = chunk * A.chunk_wrows;
   if (y0 >= F.hy) return;
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(256) nuc_eig_kernel(NucArgs A) {
   __shared__ int rank[kMaxLc];
   __shared__ double red[4];
   const NucGeom &g = A.g;
-  const int f = blockIdx.x;
+  const int f = A.eig_q < 0 ? blockIdx.x : blockIdx.x * (g.qy * g.qx) + A.eig_q;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int n = g.Lc, n2 = n + (n & 1);
   const FacetView F = facet_view(g, f);
@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
   extern __shared__ float sm[];
   __shared__ double dsh[2][kMaxSeg];
   const NucGeom &g = A.g;
-  const int q = blockIdx.y, chunk = blockIdx.x, Q = g.qy * g.qx;
+  const int q = A.q0 + blockIdx.y, chunk = blockIdx.x, Q = g.qy * g.qx;
   const FacetView F = facet_view(g, q);
   const int y0 = chunk * A.chunk_wrows;
   if (y0 >= F.hy) return;
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   extern __shared__ float sm[];
   __shared__ double dsh[2][kMaxSeg];
   const NucGeom &g = A.g;
-  const int q = blockIdx.y, chunk = blockIdx.x;
+  const int q = A.q0 + blockIdx.y, chunk = blockIdx.x;
   const FacetView F = facet_view(g, q);
   const int y0 = chunk * A.chunk_wrows;
   if (y0 >= F.hy) return;
@@ -506,8 +506,8 @@ __global__ void __launch_bounds__(256) nuc_gather_kernel(GatherArgs A) {
   __shared__ double dk[kGatherPx][4];
   __shared__ int64_t rk[kGatherPx][4];
   const NucGeom &g = A.g;
-  const int y = blockIdx.y, x0 = blockIdx.x * kGatherPx;
-  const int npx = min(kGatherPx, g.nx - x0);
+  const int y = A.y_begin + blockIdx.y, x0 = A.x_begin + blockIdx.x * kGatherPx;
+  const int npx = min(kGatherPx, A.x_end - x0);
   if (threadIdx.x < kGatherPx) {
     const int i = threadIdx.x, x = x0 + i;
 #pragma unroll
@@ -624,7 +624,7 @@ int launch_nuc_recon(const NucArgs &a, int nspatial, void *stream) {
 
 int launch_nuc_gather(const GatherArgs &a, void *stream) {
   if (a.g.L > 256) return fail(FHS_EUNSUPPORTED, "gather: more than 256 channels");
-  const dim3 grid((a.g.nx + kGatherPx - 1) / kGatherPx, a.g.ny);
+  const dim3 grid((a.x_end - a.x_begin + kGatherPx - 1) / kGatherPx, a.y_end - a.y_begin);
   hipLaunchKernelGGL(nuc_gather_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), a);
   return check_launch("nuc_gather");
 }

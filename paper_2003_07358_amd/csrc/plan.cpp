@@ -164,6 +164,19 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
         p->bands.push_back({Ky, Kx, off, j + 1});
         off += static_cast<int64_t>(Ky) * Kx;
       }
+      // coefficients of this level owned by each facet (per axis): b_j(s) =
+      // ceil((b_{j-1}(s) - 1) / 2) from the tile starts, the last facet
+      // owning the tail (the faceted transform of Sec. 2.4.2)
+      const std::vector<int> &py = j == 0 ? p->ty : p->own_y[b][j - 1];
+      const std::vector<int> &px = j == 0 ? p->tx : p->own_x[b][j - 1];
+      std::vector<int> oy(c.qy + 1), ox(c.qx + 1);
+      oy[0] = ox[0] = 0;
+      for (int sy = 1; sy < c.qy; ++sy) oy[sy] = py[sy] / 2;  // = ceil((b - 1) / 2), b >= 1
+      for (int sx = 1; sx < c.qx; ++sx) ox[sx] = px[sx] / 2;
+      oy[c.qy] = Ky;
+      ox[c.qx] = Kx;
+      p->own_y[b][j] = oy;
+      p->own_x[b][j] = ox;
       ny = Ky;
       nx = Kx;
     }

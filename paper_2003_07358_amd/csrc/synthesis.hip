@@ -131,9 +131,9 @@ __device__ __forceinline__ void syn_basis(const SynArgs &A, const SynBand &B, in
   const bool lv = lane < Lc;
   const int p = c * Lc + lane;
   const int strip = wg % B.strips, yb = wg / B.strips;
-  const int kx0 = strip * A.tk;
-  const int y0 = yb * A.ty;
-  const int y1 = min(y0 + A.ty, B.ny);
+  const int kx0 = B.x_begin / 2 + strip * A.tk;
+  const int y0 = B.y_begin + yb * A.ty;
+  const int y1 = min(y0 + A.ty, B.y_end);
   const int segn = (A.tk + H - 1) * L;
   const int segp = round_up(segn, 64);
   const int ks = y0 / 2;
@@ -164,7 +164,7 @@ __device__ __forceinline__ void syn_basis(const SynArgs &A, const SynBand &B, in
             const int y = 2 * kp + py;
 #pragma unroll
             for (int px = 0; px < 2; ++px)
-              if (lv && y < y1 && x + px < B.nx)
+              if (lv && y >= y0 && y < y1 && x + px >= B.x_begin && x + px < B.x_end)
                 B.out[(static_cast<int64_t>(y) * B.nx + x + px) * L + p] = acc[py][px];
           }
         }
@@ -274,9 +274,9 @@ syn_final_kernel(SynFinalArgs A) {
   const int p = c * Lc + lane;
   const int ch = c + lane * C;
   const int strip = blockIdx.x % A.strips, yb = blockIdx.x / A.strips;
-  const int kx0 = strip * A.tk;
-  const int y0 = yb * A.ty;
-  const int y1 = min(y0 + A.ty, A.ny);
+  const int kx0 = A.x_begin / 2 + strip * A.tk;
+  const int y0 = A.y_begin + yb * A.ty;
+  const int y1 = min(y0 + A.ty, A.y_end);
   const int ks = y0 / 2;
   const int nout = (y1 - 1) / 2 - ks + 1;
   const int x = 2 * (kx0 + kq);
@@ -301,7 +301,7 @@ syn_final_kernel(SynFinalArgs A) {
         const int y = 2 * kp + py;
         v[py][px] = 0.0f;
         gv[py][px] = 0.0f;
-        if (s >= 0 && s < nout && lv && y < y1 && x + px < A.nx) {
+        if (s >= 0 && s < nout && lv && y >= y0 && y < y1 && x + px >= A.x_begin && x + px < A.x_end) {
           const int64_t pix = static_cast<int64_t>(y) * A.nx + x + px;
           if (FIRST) {
             v[py][px] = A.dirac[pix * L + p];
@@ -344,7 +344,7 @@ syn_final_kernel(SynFinalArgs A) {
             const int y = 2 * kp + py;
 #pragma unroll
             for (int px = 0; px < 2; ++px) {
-              if (lv && y < y1 && x + px < A.nx) {
+              if (lv && y >= y0 && y < y1 && x + px >= A.x_begin && x + px < A.x_end) {
                 float *dst = A.x + (static_cast<int64_t>(y) * A.nx + x + px) * L + ch;
                 if (FIRST) {
                   const float v = scale * (acc[py][px] + vcur[py][px]);
