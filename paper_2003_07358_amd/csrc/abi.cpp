@@ -152,7 +152,7 @@ int syn_strips(int b, int e, int tk) { return e > b ? ceil_div((e - 1) / 2 - b /
 int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, float beta, void *stream, int fy = -1,
                   int fx = -1, int level = -1) {
   int tk, nth;
-  if (int rc = thread_cfg(p, &tk, &nth)) return rc;
+  if (int rc = thread_cfg(p, &tk, &nth, FHS_SYN_THREADS)) return rc;
   const int L = p->L, levels = p->cfg.levels;
   const bool facet = fy >= 0;
   for (int j = levels - 1; j >= 1; --j) {  // 0-based level j -> writes low-low band of level j-1

@@ -18,6 +18,9 @@ constexpr int kMaxLc = 64;         // channels per sub-cube
 #ifndef FHS_ANA_THREADS
 #define FHS_ANA_THREADS 512        // analysis workgroup size bound (256 or 512)
 #endif
+#ifndef FHS_SYN_THREADS
+#define FHS_SYN_THREADS 512        // synthesis workgroup size bound (256 or 512)
+#endif
 
 // ---------------------------------------------------------------- error state
 void set_error(const std::string &msg);

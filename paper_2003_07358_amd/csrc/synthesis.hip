@@ -177,7 +177,7 @@ __device__ __forceinline__ void syn_basis(const SynArgs &A, const SynBand &B, in
 }  // namespace
 
 template <int P>
-__global__ void __launch_bounds__(256) syn_kernel(SynArgs A) {
+__global__ void __launch_bounds__(FHS_SYN_THREADS) syn_kernel(SynArgs A) {
   extern __shared__ float smem[];
   const int id = blockIdx.x;
   int b = 0;
@@ -264,7 +264,7 @@ struct RingSet<BEND, BEND, P> {
 // Bases B0 .. B1-1 of level 1 summed into the image; FIRST also adds the Dirac
 // basis and applies beta, the second group accumulates onto the first.
 template <int B0, int B1, bool FIRST, int P>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FHS_FINAL_WPE)))
+__global__ void __launch_bounds__(FHS_SYN_THREADS) __attribute__((amdgpu_waves_per_eu(FHS_FINAL_WPE)))
 syn_final_kernel(SynFinalArgs A) {
   extern __shared__ float smem[];
   const int L = A.L, Lcp = A.Lcp, C = A.C, Lc = A.Lc;
