@@ -81,6 +81,7 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     a.Lcp = p->Lcp;
     a.tkx1 = tkx1;
     a.tky = p->tune.ana_rows[j];
+    a.direct = p->tune.ana_direct;
     a.mode = mode;
     a.rs = 0;
     a.lds_row = round64((2 * TKX + kMaxTap - 2) * p->L);

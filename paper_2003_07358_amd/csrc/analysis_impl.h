@@ -219,6 +219,150 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
   drain_loads();  // no LDS copy may land after the workgroup ends
 }
 
+// The same computation without LDS: every lane loads its own filter taps and
+// W / theta straight from HBM (through the caches) one step ahead into
+// registers, with range-checked buffer loads (out-of-range columns and rows
+// read as zero).  No barriers; the compiler's wait counts track each load, so
+// stores never stall a step.
+__device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+template <int NTAP, int MODE, int LCP>
+__device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B, int tile) {
+  using T = Taps<NTAP>;
+  constexpr int H = NTAP / 2;
+  if (tile >= B.strips * B.yblocks) return;
+  const int L = A.L, C = A.C, Lc = A.Lc;
+  const int tid = threadIdx.x;
+  const int lane = tid % LCP, grp = tid / LCP, c = grp % C, kq = grp / C;
+  const bool lv = lane < Lc;
+  const int p = c * Lc + lane;
+  const int chan = lv ? (B.in_natural ? c + lane * C : p) : 0;
+  const int TKX = A.tkx1;
+  const int strip = tile % B.strips, yb = tile / B.strips;
+  const int kx0 = B.kx_begin + strip * TKX, ky0 = B.ky_begin + yb * A.tky;
+  const int ky1 = min(ky0 + A.tky, B.ky_end);
+  const int kx = kx0 + kq;
+  const bool ok = lv && kx < B.kx_end;
+  const int ystart = 2 * ky0 + 2 - NTAP;
+  const int nsteps = (ky1 - ky0) + H - 1;
+  const int64_t rowlen = static_cast<int64_t>(B.in_nx) * L;
+  float thr = 0.0f;
+  if (MODE == 1) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
+  if (MODE == 2) thr = static_cast<float>(A.mu[c]);
+  // byte offset of tap NTAP-1 (column 2 kx + 2 - NTAP) of this lane in a row;
+  // tap m adds (NTAP-1-m) L 4 (negative columns wrap to huge offsets: zeros,
+  // as do columns past the row)
+  const int vbase = ((2 * kx + 2 - NTAP) * L + chan) * 4;
+  const bool last = B.ll_out == nullptr;
+  const __amdgpu_buffer_rsrc_t thr_r =
+      __builtin_amdgcn_make_buffer_rsrc(A.theta, static_cast<short>(0), static_cast<int>(A.theta_bytes), 0x00020000);
+
+  auto load_rows = [&](int g, float (&t)[2][NTAP]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int y = ystart + 2 * g + r;
+      const bool yv = g < nsteps && y >= 0 && y < B.in_ny;
+      const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float *>(B.in) + (yv ? static_cast<int64_t>(y) * rowlen : 0), static_cast<short>(0),
+          yv ? static_cast<int>(rowlen * 4) : 0, 0x00020000);
+#pragma unroll
+      // (the whole offset in voffset: the range check does not see soffset)
+      for (int m = 0; m < NTAP; ++m) t[r][m] = ld_f32(rr, vbase + (NTAP - 1 - m) * L * 4, 0);
+    }
+  };
+  // W and theta of the row emitted at step g (mode 1)
+  auto load_emit = [&](int g, float (&w)[4], float (&th)[4]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+      w[sb] = th[sb] = 0.0f;
+      if (MODE == 1) {
+        const int ky = ky0 + g - (H - 1);
+        const bool v = ok && g < nsteps && ky >= ky0 && (sb < 3 || last);
+        if (v) {
+          const int64_t rowi = B.off[sb] + static_cast<int64_t>(ky) * B.Kx + kx;
+          w[sb] = A.w[rowi * L + p];
+          th[sb] = ld_f32(thr_r, static_cast<int>((static_cast<int64_t>(c) * A.I + rowi) * 4), 0);
+        }
+      }
+    }
+  };
+
+  double rl[NTAP], rh[NTAP];
+#pragma unroll
+  for (int m = 0; m < NTAP; ++m) rl[m] = rh[m] = 0.0;
+  float ta[2][NTAP], tb[2][NTAP];
+  float wa[4], tha[4], wb[4], thb[4];
+  load_rows(0, ta);
+  load_emit(0, wa, tha);
+
+  auto step = [&](int g, const float (&t)[2][NTAP], const float (&w)[4], const float (&th)[4])
+      __attribute__((always_inline)) {
+#pragma unroll
+    for (int m = 0; m + 2 < NTAP; ++m) {
+      rl[m] = rl[m + 2];
+      rh[m] = rh[m + 2];
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      double sl = 0.0, sh = 0.0;
+#pragma unroll
+      for (int m = 0; m < NTAP; ++m) {
+        const double v = static_cast<double>(t[r][m]);
+        sl = fma(T::hd[m] * kThird, v, sl);
+        sh = fma(T::hd[NTAP - 1 - m] * kThird, (m & 1) ? -v : v, sh);
+      }
+      rl[NTAP - 2 + r] = sl;
+      rh[NTAP - 2 + r] = sh;
+    }
+    if (g >= H - 1) {
+      double ll = 0.0, lh = 0.0, hl = 0.0, hh = 0.0;
+#pragma unroll
+      for (int m = 0; m < NTAP; ++m) {
+        const double a = rl[NTAP - 1 - m], b = rh[NTAP - 1 - m];
+        ll = fma(T::hd[m], a, ll);
+        lh = fma(T::hd[m], b, lh);
+        hl = fma(T::hd[NTAP - 1 - m], (m & 1) ? -a : a, hl);
+        hh = fma(T::hd[NTAP - 1 - m], (m & 1) ? -b : b, hh);
+      }
+      const int ky = ky0 + g - (H - 1);
+      const float vb[4] = {static_cast<float>(lh), static_cast<float>(hl), static_cast<float>(hh),
+                           static_cast<float>(ll)};
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) {
+        if (sb == 3 && !last) continue;
+        const int64_t rowi = B.off[sb] + static_cast<int64_t>(ky) * B.Kx + kx;
+        if (MODE == 0) {
+          if (ok) A.w[rowi * L + p] = vb[sb];
+        } else if (MODE == 1) {
+          const float u = ok ? w[sb] + vb[sb] : 0.0f;
+          const float wn = shrink<LCP>(u, thr * th[sb]);
+          if (ok) A.w[rowi * L + p] = wn;
+        } else {
+          const float vv = ok ? vb[sb] : 0.0f;
+          const float r2 = seg_sum(vv * vv, LCP);
+          if (ok && lane == 0) A.theta[static_cast<int64_t>(c) * A.I + rowi] = thr / (sqrtf(r2) + thr);
+        }
+      }
+      if (!last && ok)
+        B.ll_out[(static_cast<int64_t>(ky) * B.Kx + kx) * L + p] = static_cast<float>(3.0 * ll);
+    }
+  };
+
+  // two steps per iteration, the register sets alternating (no copies)
+  for (int g = 0; g < nsteps; g += 2) {
+    load_rows(g + 1, tb);
+    load_emit(g + 1, wb, thb);
+    step(g, ta, wa, tha);
+    if (g + 1 < nsteps) {
+      load_rows(g + 2, ta);
+      load_emit(g + 2, wa, tha);
+      step(g + 1, tb, wb, thb);
+    }
+  }
+}
+
 // Dirac basis: coefficient row = pixel; grid-stride over pixels, 4 in flight.
 template <int MODE, int LCP>
 __device__ __forceinline__ void dirac(const AnaArgs &A, const AnaBand &B, int wg) {
@@ -274,7 +418,7 @@ __device__ __forceinline__ void dirac(const AnaArgs &A, const AnaBand &B, int wg
 
 // FIRST: level 1 (reads the cube, also handles the Dirac basis); a separate
 // instantiation so that its launches are timed and profiled on their own.
-template <bool FIRST, int MODE, int LCP>
+template <bool FIRST, int MODE, int LCP, bool DIRECT>
 __global__ void __launch_bounds__(FHS_ANA_THREADS) kernel(AnaArgs A) {
   extern __shared__ float smem[];
   const int id = blockIdx.x;
@@ -295,14 +439,14 @@ __global__ void __launch_bounds__(FHS_ANA_THREADS) kernel(AnaArgs A) {
     // static band indices, each band descriptor read into its own copy (a
     // dynamically indexed descriptor would be copied to scratch)
     switch (b) {
-      case 0: { const AnaBand B = A.b[0]; basis<2, MODE, LCP>(A, B, tile, smem); } break;
-      case 1: { const AnaBand B = A.b[1]; basis<4, MODE, LCP>(A, B, tile, smem); } break;
-      case 2: { const AnaBand B = A.b[2]; basis<6, MODE, LCP>(A, B, tile, smem); } break;
-      case 3: { const AnaBand B = A.b[3]; basis<8, MODE, LCP>(A, B, tile, smem); } break;
-      case 4: { const AnaBand B = A.b[4]; basis<10, MODE, LCP>(A, B, tile, smem); } break;
-      case 5: { const AnaBand B = A.b[5]; basis<12, MODE, LCP>(A, B, tile, smem); } break;
-      case 6: { const AnaBand B = A.b[6]; basis<14, MODE, LCP>(A, B, tile, smem); } break;
-      default: { const AnaBand B = A.b[7]; basis<16, MODE, LCP>(A, B, tile, smem); } break;
+      case 0: { const AnaBand B = A.b[0]; if (DIRECT) basis_direct<2, MODE, LCP>(A, B, tile); else basis<2, MODE, LCP>(A, B, tile, smem); } break;
+      case 1: { const AnaBand B = A.b[1]; if (DIRECT) basis_direct<4, MODE, LCP>(A, B, tile); else basis<4, MODE, LCP>(A, B, tile, smem); } break;
+      case 2: { const AnaBand B = A.b[2]; if (DIRECT) basis_direct<6, MODE, LCP>(A, B, tile); else basis<6, MODE, LCP>(A, B, tile, smem); } break;
+      case 3: { const AnaBand B = A.b[3]; if (DIRECT) basis_direct<8, MODE, LCP>(A, B, tile); else basis<8, MODE, LCP>(A, B, tile, smem); } break;
+      case 4: { const AnaBand B = A.b[4]; if (DIRECT) basis_direct<10, MODE, LCP>(A, B, tile); else basis<10, MODE, LCP>(A, B, tile, smem); } break;
+      case 5: { const AnaBand B = A.b[5]; if (DIRECT) basis_direct<12, MODE, LCP>(A, B, tile); else basis<12, MODE, LCP>(A, B, tile, smem); } break;
+      case 6: { const AnaBand B = A.b[6]; if (DIRECT) basis_direct<14, MODE, LCP>(A, B, tile); else basis<14, MODE, LCP>(A, B, tile, smem); } break;
+      default: { const AnaBand B = A.b[7]; if (DIRECT) basis_direct<16, MODE, LCP>(A, B, tile); else basis<16, MODE, LCP>(A, B, tile, smem); } break;
     }
   } else if (FIRST) {
     dirac<MODE, LCP>(A, A.b[kBases], id - A.nbase_wg);
@@ -313,12 +457,19 @@ template <int MODE>
 int launch_mode(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(static_cast<unsigned>(a.nbase_wg + (first ? a.b[kBases].strips : 0))), block(nthreads);
-#define FHS_ANA_CASE(LCP)                                                            \
-  case LCP:                                                                          \
-    if (first)                                                                       \
-      hipLaunchKernelGGL((kernel<true, MODE, LCP>), grid, block, lds, s, a);         \
-    else                                                                             \
-      hipLaunchKernelGGL((kernel<false, MODE, LCP>), grid, block, lds, s, a);        \
+#define FHS_ANA_CASE(LCP)                                                                      \
+  case LCP:                                                                                    \
+    if (a.direct) {                                                                            \
+      if (first)                                                                               \
+        hipLaunchKernelGGL((kernel<true, MODE, LCP, true>), grid, block, 0, s, a);             \
+      else                                                                                     \
+        hipLaunchKernelGGL((kernel<false, MODE, LCP, true>), grid, block, 0, s, a);            \
+    } else {                                                                                   \
+      if (first)                                                                               \
+        hipLaunchKernelGGL((kernel<true, MODE, LCP, false>), grid, block, lds, s, a);          \
+      else                                                                                     \
+        hipLaunchKernelGGL((kernel<false, MODE, LCP, false>), grid, block, lds, s, a);         \
+    }                                                                                          \
     break;
   switch (a.Lcp) {
     FHS_ANA_CASE(4)

@@ -62,6 +62,7 @@ struct AnaArgs {
   int lds_wv, lds_th;         // offsets (words) of the W and theta areas in a phase buffer
   int lds_buf;                // words per phase buffer
   int wpad, tpad;             // words per W / theta segment (multiples of 64)
+  int direct;                 // 1: taps, W and theta loaded straight into registers (no LDS staging)
   int tiles_per_xcd;          // tiles walked by each XCD
   int nbase_wg;               // 64 * tiles_per_xcd workgroups for the wavelet bases
 };

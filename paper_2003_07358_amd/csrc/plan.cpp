@@ -220,6 +220,7 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
     while (t.nuc_seg > 16 && nuc_recon_lds(p, t.nuc_seg) > 65536) t.nuc_seg /= 2;
     t.nuc_chunk_rows = std::max(1, 4096 / p->max_hx);
     t.concurrent = 1;
+    t.ana_direct = 0;
     p->nuc_chunk_min = std::max(1, t.nuc_chunk_rows / 2);
     p->gram_chunks = (p->max_hy + p->nuc_chunk_min - 1) / p->nuc_chunk_min;
   }
@@ -330,6 +331,7 @@ int fhs_plan_set_tuning(fhs_plan *p, const fhs_tuning *t) {
   if (t->nuc_chunk_rows < p->nuc_chunk_min)
     return fail(FHS_EINVAL, "nuc_chunk_rows below the workspace's minimum (" + std::to_string(p->nuc_chunk_min) + ")");
   if (t->concurrent != 0 && t->concurrent != 1) return fail(FHS_EINVAL, "concurrent must be 0 or 1");
+  if (t->ana_direct != 0 && t->ana_direct != 1) return fail(FHS_EINVAL, "ana_direct must be 0 or 1");
   p->tune = *t;
   return FHS_OK;
 }

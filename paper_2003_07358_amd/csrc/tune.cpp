@@ -71,6 +71,11 @@ extern "C" int fhs_plan_autotune(fhs_plan *p, const float *xcheck, float *pdual,
     }
     (void)fhs_plan_set_tuning(p, &best);
   };
+  for (int d : {0, 1}) {
+    fhs_tuning c = best;
+    c.ana_direct = d;
+    trial(c);
+  }
   for (int j = 0; j < p->cfg.levels && j < kMaxLevels; ++j)
     for (int rows : {16, 32, 64, 128}) {
       fhs_tuning c = best;

@@ -223,3 +223,27 @@ def test_per_facet_form_matches_batched(name):
     for nm, a, b in zip(("P+", "W+", "G"), out[1], out[0]):
         log(f"    {nm}: max |plain - batched| = {np.max(np.abs(a - b)):.3e}")
         assert np.array_equal(a, b), nm
+
+
+@pytest.mark.parametrize("name", ["cfg1_256x256x20_q2x2_o32", "ragged_101x77x6_q3x2_c2", "lc64_70x45x64_q2x1",
+                                  "tiny_7x9x3_levels2"])
+def test_direct_analysis_matches_staged(name):
+    """The LDS-free analysis (taps, W and theta loaded into registers) gives the
+    same coefficients, bit for bit, as the LDS-staged one, for every mode."""
+    pb, plan = make(name, warm=True)
+    x = dev(pb.X)
+    outs = []
+    for direct in (0, 1):
+        plan.tuning = {"ana_direct": direct}
+        w0 = torch.empty(plan.sizes["n_w"], dtype=torch.float32, device="cuda")
+        plan.sara_analysis(x, w0)
+        w1, g1 = dev(pb.W_flat()), torch.empty(plan.sizes["n_x"], device="cuda")
+        plan.l21_dual_update(x, w1, dev(pb.theta_flat()), dev(pb.mu), 1.0, g1)
+        th = torch.empty(plan.sizes["n_theta"], dtype=torch.float32, device="cuda")
+        tb = torch.empty(plan.sizes["n_theta_bar"], dtype=torch.float64, device="cuda")
+        plan.reweight(x, dev(pb.mu), dev(pb.mu_bar_flat()), th, tb)
+        outs.append([host(w0), host(w1), host(g1), host(th)])
+    for nm, a, b in zip(("Psi^dagger x", "W+", "G", "theta"), outs[1], outs[0]):
+        log(f"    {nm}: max |direct - staged| = {np.max(np.abs(a - b)):.3e}")
+        assert np.array_equal(a, b), nm
+    check("W+ (direct)", outs[1][1], np.concatenate(pb.oracle_l21()[0], axis=1).reshape(-1))
