@@ -16,13 +16,12 @@ namespace {
 constexpr int kDiracE = 4;    // pixels in flight per thread in the Dirac part of the analysis
 constexpr int kMaxDiracWg = 2048;
 #ifndef FHS_ANA_LDS_KB
-#define FHS_ANA_LDS_KB 64
+#define FHS_ANA_LDS_KB 80
 #endif
-constexpr int kAnaLdsBytes = FHS_ANA_LDS_KB * 1024;
-constexpr int kAnaThreads = FHS_ANA_THREADS;  // upper bound on analysis workgroup size  // LDS budget of an analysis workgroup (both buffers)
+constexpr int kAnaLdsBytes = FHS_ANA_LDS_KB * 1024;  // LDS budget of an analysis workgroup (two per CU)
+constexpr int kAnaThreads = FHS_ANA_THREADS;          // upper bound on analysis workgroup size
 
 int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
-int round64(int n) { return (n + 63) / 64 * 64; }
 
 float *ws_f(const fhs_plan *p, int64_t off) { return reinterpret_cast<float *>(static_cast<char *>(p->ws) + off); }
 double *ws_d(const fhs_plan *p, int64_t off) { return reinterpret_cast<double *>(static_cast<char *>(p->ws) + off); }
@@ -47,17 +46,14 @@ int64_t coef_off(const fhs_plan *p, int b, int j, int s) {  // s: 0 lh, 1 hl, 2 
 int64_t ll_off(const fhs_plan *p, int b) { return p->bands[p->band_first[b] + 3 * p->cfg.levels].off; }
 int64_t dirac_off(const fhs_plan *p) { return p->bands.back().off; }
 
-// LDS words of one phase buffer of the analysis for P steps.
+// LDS words of one phase buffer of the analysis for P steps: 2P staged rows,
+// and for the dual update 4P W row runs and 4P theta segments.
 int ana_lds_buf(const AnaArgs &a, int P) {
-  int words = round64(2 * P * a.lds_row);
-  if (a.mode == 1) words += 4 * P * (a.wpad + a.tpad);
+  int words = 2 * P * a.lds_row;
+  if (a.mode == 1) words += 4 * P * (kAnaLaneSeg + kAnaThSeg);
   return words;
 }
 
-// mode 0: w = Psi^dagger x ; mode 1: l21 dual update of w ; mode 2: theta weights
-// Facet (fy, fx) >= 0 restricts every band to the coefficients that facet
-// owns (and the Dirac band to its tile), level >= 0 to one level: the
-// per-facet execution form.
 int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, const double *mu, double inv_kappa,
                  int mode, void *stream, int fy = -1, int fx = -1, int level = -1) {
   int tkx1, nth;
@@ -83,20 +79,29 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     a.tky = p->tune.ana_rows[j];
     a.direct = p->tune.ana_direct;
     a.mode = mode;
-    a.rs = 0;
-    a.lds_row = round64((2 * TKX + kMaxTap - 2) * p->L);
-    a.wpad = round64(TKX * p->L);
-    a.tpad = round64(p->C * TKX);
+    // staged row: [sub-cube][column][lane slot], columns of the widest filter
+    // (plus one pad column per sub-cube block when there are several), in
+    // whole copy chunks (256 words with 16-byte copies, else 64)
+    a.vec4 = (p->L % 4 == 0 && p->Lc % 4 == 0) ? 1 : 0;
+    const int cw = a.vec4 ? 256 : 64;
+    const int ncp = 2 * TKX + kMaxTap - 2 + (p->C > 1 ? 1 : 0);
+    const int nchunk = ceil_div(static_cast<int64_t>(p->C) * ncp * p->Lcp, cw);
+    a.lds_row = nchunk * cw;
+    if (nth < 64) return fail(FHS_EUNSUPPORTED, "analysis: fewer than 64 threads per workgroup");
+    if (p->C * TKX > kAnaThSeg) return fail(FHS_EUNSUPPORTED, "analysis: more than 128 sub-cube columns per tile");
+    const int tab_words = nchunk * 64;
     a.P = 1;
     for (int P = p->tune.ana_phase; P >= 1; P /= 2)
-      if (2 * ana_lds_buf(a, P) * 4 <= kAnaLdsBytes || P == 1) {
+      if ((2 * ana_lds_buf(a, P) + tab_words) * 4 <= kAnaLdsBytes || P == 1) {
         a.P = P;
         break;
       }
     a.lds_buf = ana_lds_buf(a, a.P);
-    a.lds_wv = round64(2 * a.P * a.lds_row);
-    a.lds_th = a.lds_wv + 4 * a.P * a.wpad;
-    if (2 * a.lds_buf * 4 > 160 * 1024) return fail(FHS_EUNSUPPORTED, "analysis: LDS tile exceeds 160 KB");
+    a.lds_wv = 2 * a.P * a.lds_row;
+    a.lds_th = a.lds_wv + 4 * a.P * kAnaLaneSeg;
+    a.lds_tab = 2 * a.lds_buf;
+    a.lds_words = a.lds_tab + tab_words;
+    if (a.lds_words * 4 > 160 * 1024) return fail(FHS_EUNSUPPORTED, "analysis: LDS tile exceeds 160 KB");
     int tmax = 0;
     for (int b = 0; b < kBases; ++b) {
       AnaBand &B = a.b[b];

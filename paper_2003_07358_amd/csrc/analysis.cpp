@@ -6,7 +6,7 @@ namespace fhs {
 
 int launch_analysis(const AnaArgs &a, int nthreads, bool first, void *stream) {
   if (a.nbase_wg <= 0 && !(first && a.b[kBases].strips > 0)) return FHS_OK;
-  const size_t lds = static_cast<size_t>(2 * a.lds_buf) * sizeof(float);
+  const size_t lds = static_cast<size_t>(a.lds_words) * sizeof(float);
   switch (a.mode) {
     case 0: return launch_analysis_m0(a, nthreads, first, lds, stream);
     case 1: return launch_analysis_m1(a, nthreads, first, lds, stream);

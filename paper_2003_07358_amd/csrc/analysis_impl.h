@@ -16,20 +16,29 @@
 // NTAP rows filters vertically to emit one coefficient row of the four bands.
 //
 // Memory pipeline: steps are grouped into phases of P steps.  Per phase, the
-// 2P input row segments and the W / theta values of the P emitted rows are
-// copied HBM -> LDS by buffer loads whose destination is LDS, one phase ahead
-// into a double buffer; one barrier per phase.  A row segment is one
-// contiguous run of HBM ([column][channel]), copied as is.
+// 2P input row segments (and, for the dual update, the W and theta values of
+// the P emitted rows) are copied HBM -> LDS by buffer loads whose destination
+// is LDS, one phase ahead into a double buffer; one barrier per phase.  A
+// staged row is laid out [sub-cube][column][lane slot] with LCP slots per
+// column, so that the taps of a lane sit at compile-time offsets from one
+// address (padding slots and columns outside the band read as zero); each
+// lane's W and theta values are staged at its own thread index.  The results
+// leave through range-checked buffer stores (out-of-range lanes are dropped),
+// a fixed four per emitted row, so that the wait at a phase boundary can leave
+// the previous phase's stores in flight.
 //
 // Launch order is XCD-aware: workgroup id -> XCD id % 8; each XCD walks a
 // contiguous run of tiles and, for each tile, the 8 bases one after the other,
 // so the input segments of a tile are fetched from HBM once per XCD L2.
 //
-// Precision: FP32 in / FP32 out, FP64 accumulation (detail coefficients are
-// differences of large neighbouring values).
+// Arithmetic: FP32 in / FP32 out, FP64 accumulation (detail coefficients are
+// differences of large neighbouring values), unnormalised filters with the
+// 1/3 applied to each emitted coefficient.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "fhs_filters.h"
 #include "fhs_internal.h"
@@ -40,6 +49,7 @@ namespace ana {
 
 constexpr double kThird = 1.0 / 3.0;  // 1 / sqrt(9): nine bases
 constexpr int kMaxPhase = 4;          // steps per LDS phase, upper bound (the launch picks P)
+constexpr int kOob = static_cast<int>(0x80000000u);  // buffer offset past any range: loads 0, stores dropped
 
 typedef __attribute__((address_space(3))) unsigned int lds_u32;
 
@@ -57,165 +67,325 @@ __device__ __forceinline__ float shrink(float u, float thr_th) {
   return u * fminf(1.0f, thr_th * __frsqrt_rn(r2));
 }
 
+// Horizontal filters of one input row at one output column: lo = sum_m h[m]
+// v_m and hi = sum_m g[m] v_m, g[m] = (-1)^m h[NTAP-1-m], where v_m = tap(m)
+// is the input at column 2k+1-m.  The high-pass sign stays off the constants
+// (even and odd terms are summed apart), so only the NTAP values h[m] are live.
+template <int NTAP, typename F>
+__device__ __forceinline__ void hfilt(F &&tap, double &lo, double &hi) {
+  using T = Taps<NTAP>;
+  double sl = 0.0, se = 0.0, so = 0.0;
+#pragma unroll
+  for (int m = 0; m < NTAP; ++m) {
+    const double v = static_cast<double>(tap(m));
+    sl = fma(T::hd[m], v, sl);
+    if (m & 1)
+      so = fma(T::hd[NTAP - 1 - m], v, so);
+    else
+      se = fma(T::hd[NTAP - 1 - m], v, se);
+  }
+  lo = sl;
+  hi = se - so;
+}
+
+// Vertical filters over the ring (ra(m), rb(m): the low and high horizontal
+// outputs of the row that tap m multiplies): ll, lh through h, hl, hh through g.
+template <int NTAP, typename FA, typename FB>
+__device__ __forceinline__ void vfilt(FA &&ra, FB &&rb, double &ll, double &lh, double &hl, double &hh) {
+  using T = Taps<NTAP>;
+  double sll = 0.0, slh = 0.0, ae = 0.0, ao = 0.0, be = 0.0, bo = 0.0;
+#pragma unroll
+  for (int m = 0; m < NTAP; ++m) {
+    const double a = ra(m), b = rb(m);
+    sll = fma(T::hd[m], a, sll);
+    slh = fma(T::hd[m], b, slh);
+    if (m & 1) {
+      ao = fma(T::hd[NTAP - 1 - m], a, ao);
+      bo = fma(T::hd[NTAP - 1 - m], b, bo);
+    } else {
+      ae = fma(T::hd[NTAP - 1 - m], a, ae);
+      be = fma(T::hd[NTAP - 1 - m], b, be);
+    }
+  }
+  ll = sll;
+  lh = slh;
+  hl = ae - ao;
+  hh = be - bo;
+}
+
+__device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void st_f32(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+// Raw buffer over [base, base + bytes): offsets at or past `bytes` read zero
+// and drop their stores.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), static_cast<short>(0), static_cast<int>(bytes),
+                                           0x00020000);
+}
+
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), in order.
+template <int I, int N>
+struct Unroll {
+  template <typename F>
+  __device__ __forceinline__ static void run(F &&f) {
+    f(std::integral_constant<int, I>{});
+    Unroll<I + 1, N>::run(f);
+  }
+};
+template <int N>
+struct Unroll<N, N> {
+  template <typename F>
+  __device__ __forceinline__ static void run(F &&) {}
+};
+template <int N, typename F>
+__device__ __forceinline__ void unroll_steps(F &&f) {
+  Unroll<0, N>::run(f);
+}
+
+#ifndef FHS_ANA_ROTATE
+#define FHS_ANA_ROTATE 0  // 1: ring slots rotate with the step (loop unrolled over NTAP/2 steps)
+#endif
+
+// Workgroup barrier without a memory fence (the copies are waited for by
+// count before it; LDS accesses are not moved across it).
+__device__ __forceinline__ void barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Waits until at most n (0, 4, 8 or 16) of this wave's vector-memory
+// operations are outstanding.  They complete in issue order, so the n most
+// recent may stay in flight.
+__device__ __forceinline__ void wait_vm_but(int n) {
+  if (n == 4)
+    asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+  else if (n == 8)
+    asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+  else if (n == 16)
+    asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+  else
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 template <int NTAP, int MODE, int LCP>
 __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int tile, float *smem) {
-  using T = Taps<NTAP>;
   constexpr int H = NTAP / 2;
   if (tile >= B.strips * B.yblocks) return;
   const int L = A.L, C = A.C, Lc = A.Lc, P = A.P;
   const int tid = threadIdx.x;
   const int lane = tid % LCP, grp = tid / LCP, c = grp % C, kq = grp / C;
-  const bool lv = lane < Lc;
   const int p = c * Lc + lane;
-  const int chan = lv ? (B.in_natural ? c + lane * C : p) : 0;
   const int TKX = A.tkx1;
   const int strip = tile % B.strips, yb = tile / B.strips;
   const int kx0 = B.kx_begin + strip * TKX, ky0 = B.ky_begin + yb * A.tky;
   const int ky1 = min(ky0 + A.tky, B.ky_end);
-  const int kx = kx0 + kq;
-  const bool ok = lv && kx < B.kx_end;
-  const int NC = 2 * TKX + NTAP - 2;        // input columns of a row segment
-  const int ROW = A.lds_row;                // LDS words per staged input row
-  const int col0 = 2 * kx0 + 2 - NTAP;      // first input column
+  const int nkx = min(TKX, B.kx_end - kx0);     // coefficient columns of the tile
+  const bool ok = lane < Lc && kq < nkx;
+  const int NC = 2 * TKX + NTAP - 2;            // input columns of a staged row
+  const int NCP = NC + (C > 1 ? 1 : 0);         // columns per sub-cube block (one pad column spreads the
+                                                // sub-cube blocks over the LDS banks)
+  // 16-byte copies when the channels of a column segment are contiguous and
+  // 16-byte aligned, else 4-byte copies; a chunk is one copy instruction
+  const bool v4 = A.vec4 && (C == 1 || !B.in_natural);
+  const int cw = v4 ? 256 : 64;                 // words per chunk
+  const int nchunk = (C * NCP * LCP + cw - 1) / cw;
+  const int ROW = A.lds_row;
+  const int col0 = 2 * kx0 + 2 - NTAP;          // first input column
   const int ystart = 2 * ky0 + 2 - NTAP;
   const int nsteps = (ky1 - ky0) + H - 1;
   const int nph = (nsteps + P - 1) / P;
-  const int64_t rowlen = static_cast<int64_t>(B.in_nx) * L;
-  const int KxL = B.Kx * L;
+  const uint32_t row_bytes = static_cast<uint32_t>(B.in_nx) * L * 4;
+  const bool last = B.ll_out == nullptr;
+  const uint32_t run_bytes = static_cast<uint32_t>(nkx * L * 4);  // one coefficient row run of the tile
+  const uint64_t band_row = static_cast<uint64_t>(B.Kx) * L * 4;  // bytes per coefficient row of a band
   float thr = 0.0f;
   if (MODE == 1) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
   if (MODE == 2) thr = static_cast<float>(A.mu[c]);
+  const int wv = wave_id(), nwv = full_wave_count(), ln = tid & 63;
 
-  // ---- copy plan (per lane, fixed for the workgroup)
-  const int wv = wave_id(), nwv = full_wave_count();
-  const int ln = threadIdx.x & 63;
-  const int64_t seg0 = static_cast<int64_t>(col0) * L;  // first float of a row segment
-  const int segn = NC * L;                               // floats of a row segment
-  // theta gather: word i = 64 j + ln -> (sub-cube i / TKX, column kx0 + i % TKX); C * TKX <= 128
+  // byte addresses of the tile's first column in coefficient row 0 of each
+  // band (W) and of the low-low output; theta row offsets of the bands
+  const char *wbase[4];
+  int32_t tbase[4];
+#pragma unroll
+  for (int sb = 0; sb < 4; ++sb) {
+    // (explicit select: a dynamic index into the band descriptor would copy it to scratch)
+    const int64_t boff = sb == 0 ? B.off[0] : sb == 1 ? B.off[1] : sb == 2 ? B.off[2] : B.off[3];
+    wbase[sb] = reinterpret_cast<const char *>(A.w + (boff + kx0) * L);
+    tbase[sb] = static_cast<int32_t>(boff * 4);
+  }
+  const char *llbase = reinterpret_cast<const char *>(B.ll_out + static_cast<int64_t>(kx0) * L);
+
+  // buffer offsets of this lane: its word in a coefficient row run of the
+  // tile (W, low-low output) and its theta word (sub-cube c, column kx)
+  const int wl = kq * L + p;
+  const int vo = ok ? wl * 4 : kOob;
+  const int vth = ok ? static_cast<int>((static_cast<int64_t>(c) * A.I + kx0 + kq) * 4) : kOob;
+  const int vth0 = lane == 0 ? vth : kOob;
+  // theta copy: word i = 64 j + ln of a segment -> (sub-cube i / TKX, column i % TKX)
   int th_voff[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int i = 64 * j + ln, cc = i / TKX, kk = i - cc * TKX;
-    th_voff[j] = (cc < C && kx0 + kk < B.kx_end) ? static_cast<int>((static_cast<int64_t>(cc) * A.I + kx0 + kk) * 4)
-                                             : static_cast<int>(0x80000000u);
+    th_voff[j] = (cc < C && kk < nkx) ? static_cast<int>((static_cast<int64_t>(cc) * A.I + kx0 + kk) * 4) : kOob;
   }
-  const int nth_chunks = (C * TKX + 63) / 64;
+  const int nth_chunks = (C * TKX + 63) >> 6;
 
+  // copy table (all waves build it): for chunk i of a staged row, lane ln's
+  // byte offset in the input row, or out of range
+  int *tab = reinterpret_cast<int *>(smem + A.lds_tab);
+  for (int e = tid; e < nchunk * 64; e += blockDim.x) {
+    const int s0 = (e >> 6) * cw + (e & 63) * (cw >> 6);  // first slot of the lane's copy
+    const int ls = s0 % LCP, q = s0 / LCP, cc = q / NCP, col = q - cc * NCP, gc = col0 + col;
+    int off = kOob;
+    if (cc < C && col < NC && ls < Lc && gc >= 0 && gc < B.in_nx)
+      off = (gc * L + (B.in_natural ? cc + ls * C : cc * Lc + ls)) * 4;
+    tab[e] = off;
+  }
+  __syncthreads();
+  const int *tabl = tab + ln;
+
+  // one phase of copies: the 2P input rows (one wave each), and for the dual
+  // update the W run and the theta values of each row emitted in the phase
+  // (one wave per band and row), spread over the full waves
+  const int ntask = 2 * P + (MODE == 1 ? 8 * P : 0);
   auto issue_phase = [&](int ph) __attribute__((always_inline)) {
-    if (wv >= nwv) return;
     float *buf = smem + (ph & 1) * A.lds_buf;
-    const int ntask = 2 * P + (MODE == 1 ? 4 * P : 0);
-    for (int t = wv; t < ntask; t += nwv) {
+    for (int t = wv; t < ntask && wv < nwv; t += nwv) {
       if (t < 2 * P) {
         const int y = ystart + 2 * P * ph + t;
         const bool yv = y >= 0 && y < B.in_ny;
-        wave_copy_row(B.in + (yv ? static_cast<int64_t>(y) * rowlen : 0), rowlen, seg0, segn, yv, buf + t * ROW);
+        const fhs_int32x4 rs =
+            buffer_rsrc(reinterpret_cast<const char *>(B.in) + (yv ? static_cast<uint64_t>(y) * row_bytes : 0),
+                        yv ? row_bytes : 0u);
+        float *dst = buf + t * ROW;
+        if (v4) {
+          for (int i = 0; i < nchunk; ++i) fhs_raw_buffer_load_lds(rs, lds_ptr(dst + 256 * i), 16, tabl[64 * i], 0, 0, 0);
+        } else {
+          for (int i = 0; i < nchunk; ++i) fhs_raw_buffer_load_lds(rs, lds_ptr(dst + 64 * i), 4, tabl[64 * i], 0, 0, 0);
+        }
       } else {
-        const int k = (t - 2 * P) >> 2, s = (t - 2 * P) & 3;
+        const int u = t - 2 * P, k = u >> 3, sb = u & 3;
         const int g = P * ph + k;
+        if (g >= nsteps || g < H - 1 || (sb == 3 && !last)) continue;
         const int ky = ky0 + g - (H - 1);
-        // (explicit select: a dynamic index into the band descriptor would copy it to scratch)
-        const int64_t boff = s == 0 ? B.off[0] : s == 1 ? B.off[1] : s == 2 ? B.off[2] : B.off[3];
-        if (g >= nsteps || ky < 0 || ky >= B.Ky || boff < 0) continue;
-        const int64_t rowi = boff + static_cast<int64_t>(ky) * B.Kx + kx0;  // first coefficient row
-        // W of the TKX coefficient rows: TKX * L contiguous floats
-        const int nw = min(TKX, B.kx_end - kx0) * L;
-        const fhs_int32x4 wr = buffer_rsrc(A.w + rowi * L, static_cast<unsigned>(nw * 4));
-        float *wdst = buf + A.lds_wv + (4 * k + s) * A.wpad;
-        for (int j = 0; j < A.wpad; j += 64)
-          fhs_raw_buffer_load_lds(wr, lds_ptr(wdst + j), 4, (j + ln) * 4, 0, 0, 0);
-        // theta of the same rows for every sub-cube: a gather
-        const fhs_int32x4 tr = buffer_rsrc(A.theta, static_cast<unsigned>(A.theta_bytes));
-        float *tdst = buf + A.lds_th + (4 * k + s) * A.tpad;
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          if (j < nth_chunks)
-            fhs_raw_buffer_load_lds(tr, lds_ptr(tdst + 64 * j), 4, th_voff[j],
-                                    static_cast<int>((boff + static_cast<int64_t>(ky) * B.Kx) * 4), 0, 0);
+        const int64_t boff = sb == 0 ? B.off[0] : sb == 1 ? B.off[1] : sb == 2 ? B.off[2] : B.off[3];
+        if ((u & 4) == 0) {
+          // W run of the row: nkx L contiguous floats
+          const fhs_int32x4 wr = buffer_rsrc(reinterpret_cast<const char *>(A.w + (boff + kx0) * L) +
+                                                 static_cast<uint64_t>(ky) * band_row,
+                                             run_bytes);
+          float *dst = buf + A.lds_wv + (4 * k + sb) * kAnaLaneSeg;
+          if (A.vec4)
+            for (int j = 0; j < kAnaLaneSeg; j += 256) fhs_raw_buffer_load_lds(wr, lds_ptr(dst + j), 16, (j + 4 * ln) * 4, 0, 0, 0);
+          else
+            for (int j = 0; j < kAnaLaneSeg; j += 64) fhs_raw_buffer_load_lds(wr, lds_ptr(dst + j), 4, (j + ln) * 4, 0, 0, 0);
+        } else {
+          // theta of the row for every sub-cube: a gather
+          const fhs_int32x4 tr = buffer_rsrc(A.theta, static_cast<unsigned>(A.theta_bytes));
+          float *dst = buf + A.lds_th + (4 * k + sb) * kAnaThSeg;
+          const int so = static_cast<int>((boff + static_cast<int64_t>(ky) * B.Kx) * 4);
+          fhs_raw_buffer_load_lds(tr, lds_ptr(dst), 4, th_voff[0], so, 0, 0);
+          if (nth_chunks > 1) fhs_raw_buffer_load_lds(tr, lds_ptr(dst + 64), 4, th_voff[1], so, 0, 0);
+        }
       }
     }
   };
 
+  // ring of horizontal outputs: slot i % NTAP holds input row i (relative to
+  // the first needed row); the loop below is unrolled over H steps, so that
+  // every slot index is a compile-time constant and no entry moves
   double rl[NTAP], rh[NTAP];
 #pragma unroll
   for (int m = 0; m < NTAP; ++m) rl[m] = rh[m] = 0.0;
-  // LDS word of tap NTAP-1 (the lowest column) of this lane in an input row
-  const int lbase = 2 * kq * L + chan;
-  const int wl = kq * L + p;                 // lane's word in a W row segment
-  const int tl = c * TKX + kq;               // lane's word in a theta segment
+  // LDS word of tap NTAP-1 (the lowest column) of this lane in a staged row
+  const int lb = (c * NCP + 2 * kq) * LCP + lane;
+  const int tl = c * TKX + kq;  // lane's word in a theta segment
 
   issue_phase(0);
-  for (int ph = 0; ph < nph; ++ph) {
-    wait_loads_and_sync();
-    if (ph + 1 < nph) issue_phase(ph + 1);
+  int ph = 0, k = 0;
+  // step g at ring rotation S (= g mod H when the loop is unrolled over H
+  // steps, else H-1 after a shift of the ring by two)
+  auto step = [&](auto S, int g) __attribute__((always_inline)) {
+    constexpr int s = decltype(S)::value;
+    if (k == 0) {
+      // the phase's copies were issued before the previous phase's 4P
+      // stores, the only later vector-memory operations of this wave; the
+      // barrier itself waits for nothing
+      if (ph == 0)
+        wait_vm_but(0);
+      else
+        wait_vm_but(4 * P);
+      barrier();
+      if (ph + 1 < nph) issue_phase(ph + 1);
+    }
     const float *buf = smem + (ph & 1) * A.lds_buf;
 #pragma unroll
-    for (int k = 0; k < kMaxPhase; ++k) {
-      const int g = ph * P + k;
-      if (k < P && g < nsteps) {
-        // horizontal filter of the step's two rows; the ring shifts by two
-        // (entry NTAP-1-m holds input row 2g+1-m once filled)
+    for (int r = 0; r < 2; ++r) {
+      const float *rp = buf + (2 * k + r) * ROW + lb;
+      hfilt<NTAP>([&](int m) { return rp[(NTAP - 1 - m) * LCP]; }, rl[2 * s + r], rh[2 * s + r]);
+    }
+    if (g >= H - 1) {
+      // tap m multiplies input row 2g+1-m, slot (2s+1-m) mod NTAP
+      double ll, lh, hl, hh;
+      vfilt<NTAP>([&](int m) { return rl[(2 * s + 1 - m + NTAP) % NTAP]; },
+                  [&](int m) { return rh[(2 * s + 1 - m + NTAP) % NTAP]; }, ll, lh, hl, hh);
+      const int ky = ky0 + g - (H - 1);
+      const uint64_t rb = static_cast<uint64_t>(ky) * band_row;
+      const float vb[4] = {static_cast<float>(lh * kThird), static_cast<float>(hl * kThird),
+                           static_cast<float>(hh * kThird), static_cast<float>(ll * kThird)};
+      const float *wsg = buf + A.lds_wv + 4 * k * kAnaLaneSeg + wl;
+      const float *tsg = buf + A.lds_th + 4 * k * kAnaThSeg + tl;
+      // exactly four stores per emitted row (the phase wait counts them)
 #pragma unroll
-        for (int m = 0; m + 2 < NTAP; ++m) {
-          rl[m] = rl[m + 2];
-          rh[m] = rh[m + 2];
-        }
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          // taps: h / 3 (the dictionary's 1/3 applied here), and g[m] =
-          // (-1)^m h[NTAP-1-m] written with the sign on the data, so that only
-          // NTAP distinct constants are live
-          const float *bp = buf + (2 * k + r) * ROW + lbase;
-          double sl = 0.0, sh = 0.0;
-#pragma unroll
-          for (int m = 0; m < NTAP; ++m) {
-            const double v = static_cast<double>(bp[(NTAP - 1 - m) * L]);
-            sl = fma(T::hd[m] * kThird, v, sl);
-            sh = fma(T::hd[NTAP - 1 - m] * kThird, (m & 1) ? -v : v, sh);
-          }
-          rl[NTAP - 2 + r] = sl;
-          rh[NTAP - 2 + r] = sh;
-        }
-        if (g >= H - 1) {
-          // (the ring holds rows already divided by 3)
-          double ll = 0.0, lh = 0.0, hl = 0.0, hh = 0.0;
-#pragma unroll
-          for (int m = 0; m < NTAP; ++m) {
-            const double a = rl[NTAP - 1 - m], b = rh[NTAP - 1 - m];
-            ll = fma(T::hd[m], a, ll);
-            lh = fma(T::hd[m], b, lh);
-            hl = fma(T::hd[NTAP - 1 - m], (m & 1) ? -a : a, hl);
-            hh = fma(T::hd[NTAP - 1 - m], (m & 1) ? -b : b, hh);
-          }
-          const int ky = ky0 + g - (H - 1);
-          const float vb[4] = {static_cast<float>(lh), static_cast<float>(hl), static_cast<float>(hh),
-                               static_cast<float>(ll)};
-          const bool last = B.ll_out == nullptr;
-#pragma unroll
-          for (int sb = 0; sb < 4; ++sb) {
-            if (sb == 3 && !last) continue;
-            const int64_t rowi = B.off[sb] + static_cast<int64_t>(ky) * B.Kx + kx0;
-            float *wrow = A.w + rowi * L;
-            if (MODE == 0) {
-              if (ok) wrow[wl] = vb[sb];
-            } else if (MODE == 1) {
-              const float wold = buf[A.lds_wv + (4 * k + sb) * A.wpad + wl];
-              const float th = buf[A.lds_th + (4 * k + sb) * A.tpad + tl];
-              const float u = ok ? wold + vb[sb] : 0.0f;
-              const float wn = shrink<LCP>(u, thr * th);
-              if (ok) wrow[wl] = wn;
-            } else {
-              const float vv = ok ? vb[sb] : 0.0f;
-              const float r2 = seg_sum(vv * vv, LCP);
-              if (ok && lane == 0) A.theta[static_cast<int64_t>(c) * A.I + rowi + kq] = thr / (sqrtf(r2) + thr);
-            }
-          }
-          if (B.ll_out && ok)
-            B.ll_out[static_cast<int64_t>(ky) * KxL + static_cast<int64_t>(kx) * L + p] = static_cast<float>(3.0 * ll);
+      for (int sb = 0; sb < 4; ++sb) {
+        if (sb == 3 && !last) continue;
+        if (MODE == 0) {
+          st_f32(vb[sb], rsrc(wbase[sb] + rb, run_bytes), vo, 0);
+        } else if (MODE == 1) {
+          const float wold = wsg[sb * kAnaLaneSeg], th = tsg[sb * kAnaThSeg];
+          const float u = lane < Lc ? wold + vb[sb] : 0.0f;
+          st_f32(shrink<LCP>(u, thr * th), rsrc(wbase[sb] + rb, run_bytes), vo, 0);
+        } else {
+          const float r2 = seg_sum(vb[sb] * vb[sb], LCP);
+          st_f32(thr / (sqrtf(r2) + thr), rsrc(A.theta, static_cast<uint32_t>(A.theta_bytes)), vth0,
+                 tbase[sb] + ky * B.Kx * 4);
         }
       }
+      if (!last) st_f32(static_cast<float>(ll), rsrc(llbase + rb, run_bytes), vo, 0);
+    } else {
+      // (steps that fill the ring issue four dropped stores, so that every
+      // step issues exactly four; distinct, non-adjacent offsets keep the
+      // compiler from merging or eliminating them)
+      const __amdgpu_buffer_rsrc_t none = rsrc(A.w, 0u);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) st_f32(0.0f, none, kOob + 1024 * i, 0);
     }
+    if (++k == P) {
+      k = 0;
+      ++ph;
+    }
+  };
+#if FHS_ANA_ROTATE
+  for (int g0 = 0; g0 < nsteps; g0 += H)
+    unroll_steps<H>([&](auto S) __attribute__((always_inline)) {
+      const int g = g0 + decltype(S)::value;
+      if (g < nsteps) step(S, g);
+    });
+#else
+  for (int g = 0; g < nsteps; ++g) {
+#pragma unroll
+    for (int m = 0; m + 2 < NTAP; ++m) {
+      rl[m] = rl[m + 2];
+      rh[m] = rh[m + 2];
+    }
+    step(std::integral_constant<int, H - 1>{}, g);
   }
+#endif
   drain_loads();  // no LDS copy may land after the workgroup ends
 }
 
@@ -224,13 +394,9 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
 // registers, with range-checked buffer loads (out-of-range columns and rows
 // read as zero).  No barriers; the compiler's wait counts track each load, so
 // stores never stall a step.
-__device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
 
 template <int NTAP, int MODE, int LCP>
 __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B, int tile) {
-  using T = Taps<NTAP>;
   constexpr int H = NTAP / 2;
   if (tile >= B.strips * B.yblocks) return;
   const int L = A.L, C = A.C, Lc = A.Lc;
@@ -305,30 +471,14 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
       rh[m] = rh[m + 2];
     }
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      double sl = 0.0, sh = 0.0;
-#pragma unroll
-      for (int m = 0; m < NTAP; ++m) {
-        const double v = static_cast<double>(t[r][m]);
-        sl = fma(T::hd[m] * kThird, v, sl);
-        sh = fma(T::hd[NTAP - 1 - m] * kThird, (m & 1) ? -v : v, sh);
-      }
-      rl[NTAP - 2 + r] = sl;
-      rh[NTAP - 2 + r] = sh;
-    }
+    for (int r = 0; r < 2; ++r) hfilt<NTAP>([&](int m) { return t[r][m]; }, rl[NTAP - 2 + r], rh[NTAP - 2 + r]);
     if (g >= H - 1) {
-      double ll = 0.0, lh = 0.0, hl = 0.0, hh = 0.0;
-#pragma unroll
-      for (int m = 0; m < NTAP; ++m) {
-        const double a = rl[NTAP - 1 - m], b = rh[NTAP - 1 - m];
-        ll = fma(T::hd[m], a, ll);
-        lh = fma(T::hd[m], b, lh);
-        hl = fma(T::hd[NTAP - 1 - m], (m & 1) ? -a : a, hl);
-        hh = fma(T::hd[NTAP - 1 - m], (m & 1) ? -b : b, hh);
-      }
+      double ll, lh, hl, hh;
+      vfilt<NTAP>([&](int m) { return rl[NTAP - 1 - m]; }, [&](int m) { return rh[NTAP - 1 - m]; }, ll, lh, hl,
+                  hh);
       const int ky = ky0 + g - (H - 1);
-      const float vb[4] = {static_cast<float>(lh), static_cast<float>(hl), static_cast<float>(hh),
-                           static_cast<float>(ll)};
+      const float vb[4] = {static_cast<float>(lh * kThird), static_cast<float>(hl * kThird),
+                           static_cast<float>(hh * kThird), static_cast<float>(ll * kThird)};
 #pragma unroll
       for (int sb = 0; sb < 4; ++sb) {
         if (sb == 3 && !last) continue;
@@ -336,17 +486,16 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
         if (MODE == 0) {
           if (ok) A.w[rowi * L + p] = vb[sb];
         } else if (MODE == 1) {
-          const float u = ok ? w[sb] + vb[sb] : 0.0f;
-          const float wn = shrink<LCP>(u, thr * th[sb]);
+          // (lanes past Lc load channel 0: kept out of the norm)
+          const float wn = shrink<LCP>(lv ? w[sb] + vb[sb] : 0.0f, thr * th[sb]);
           if (ok) A.w[rowi * L + p] = wn;
         } else {
-          const float vv = ok ? vb[sb] : 0.0f;
+          const float vv = lv ? vb[sb] : 0.0f;
           const float r2 = seg_sum(vv * vv, LCP);
           if (ok && lane == 0) A.theta[static_cast<int64_t>(c) * A.I + rowi] = thr / (sqrtf(r2) + thr);
         }
       }
-      if (!last && ok)
-        B.ll_out[(static_cast<int64_t>(ky) * B.Kx + kx) * L + p] = static_cast<float>(3.0 * ll);
+      if (!last && ok) B.ll_out[(static_cast<int64_t>(ky) * B.Kx + kx) * L + p] = static_cast<float>(ll);
     }
   };
 
@@ -419,7 +568,11 @@ __device__ __forceinline__ void dirac(const AnaArgs &A, const AnaBand &B, int wg
 // FIRST: level 1 (reads the cube, also handles the Dirac basis); a separate
 // instantiation so that its launches are timed and profiled on their own.
 template <bool FIRST, int MODE, int LCP, bool DIRECT>
-__global__ void __launch_bounds__(FHS_ANA_THREADS) kernel(AnaArgs A) {
+#ifndef FHS_ANA_WAVES_PER_EU
+#define FHS_ANA_WAVES_PER_EU 4  // register budget: 128 VGPRs (two 512-thread workgroups per CU)
+#endif
+__global__ void __launch_bounds__(FHS_ANA_THREADS) __attribute__((amdgpu_waves_per_eu(FHS_ANA_WAVES_PER_EU)))
+kernel(AnaArgs A) {
   extern __shared__ float smem[];
   const int id = blockIdx.x;
   if (id < A.nbase_wg) {

@@ -18,6 +18,9 @@ constexpr int kMaxLc = 64;         // channels per sub-cube
 #ifndef FHS_ANA_THREADS
 #define FHS_ANA_THREADS 512        // analysis workgroup size bound (256 or 512)
 #endif
+constexpr int kAnaLaneSeg = 512;   // LDS words of one staged W row run (TKX L <= threads per workgroup)
+constexpr int kAnaThSeg = 128;     // LDS words of one staged theta segment (C TKX <= threads / 4)
+static_assert(FHS_ANA_THREADS <= kAnaLaneSeg, "analysis W segments hold up to one word per thread");
 #ifndef FHS_SYN_THREADS
 #define FHS_SYN_THREADS 512        // synthesis workgroup size bound (256 or 512)
 #endif
@@ -57,11 +60,12 @@ struct AnaArgs {
   int L, C, Lc, Lcp, tkx1, tky;
   int mode;                   // 0: write Psi^dagger x; 1: l21 dual update; 2: l21 weights
   int P;                      // steps per LDS phase
-  int rs;                     // LDS words per channel of an input row segment (odd)
-  int lds_row;                // L * rs
+  int lds_row;                // words per staged input row ([sub-cube][column][lane slot], 16-tap width)
   int lds_wv, lds_th;         // offsets (words) of the W and theta areas in a phase buffer
   int lds_buf;                // words per phase buffer
-  int wpad, tpad;             // words per W / theta segment (multiples of 64)
+  int lds_tab;                // offset (words) of the row copy table (after both buffers)
+  int lds_words;              // LDS words of the launch
+  int vec4;                   // 1: channel counts allow 16-byte copies (L and Lc multiples of 4)
   int direct;                 // 1: taps, W and theta loaded straight into registers (no LDS staging)
   int tiles_per_xcd;          // tiles walked by each XCD
   int nbase_wg;               // 64 * tiles_per_xcd workgroups for the wavelet bases
