@@ -13,8 +13,7 @@ using namespace fhs;
 
 namespace {
 
-constexpr int kDiracE = 4;    // pixels in flight per thread in the Dirac part of the analysis
-constexpr int kMaxDiracWg = 2048;
+constexpr int kMaxDiracWg = 8192;
 #ifndef FHS_ANA_LDS_KB
 #define FHS_ANA_LDS_KB 80
 #endif
@@ -136,9 +135,10 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       D.ky_end = facet ? p->ty[fy + 1] : p->cfg.ny;
       D.kx_begin = facet ? p->tx[fx] : 0;
       D.kx_end = facet ? p->tx[fx + 1] : p->cfg.nx;
-      // grid-stride workgroups for the Dirac band (kDiracE pixels in flight per thread)
+      // grid-stride workgroups of the Dirac-band kernel (kDiracE pixels in flight per thread)
       const int64_t npix = static_cast<int64_t>(D.ky_end - D.ky_begin) * (D.kx_end - D.kx_begin);
-      D.strips = std::max(1, std::min(kMaxDiracWg, ceil_div(npix, static_cast<int64_t>(kDiracE) * TKX)));
+      const int ppw = kDiracThreads / (p->C * p->Lcp);
+      D.strips = npix > 0 ? std::max(1, std::min(kMaxDiracWg, ceil_div(npix, static_cast<int64_t>(kDiracE) * ppw))) : 0;
     }
     const int kid = j == 0 ? FHS_K_ANALYSIS_L1 : FHS_K_ANALYSIS;
     prof_begin(p, kid, stream);

@@ -146,7 +146,7 @@ __device__ __forceinline__ void unroll_steps(F &&f) {
 }
 
 #ifndef FHS_ANA_ROTATE
-#define FHS_ANA_ROTATE 0  // 1: ring slots rotate with the step (loop unrolled over NTAP/2 steps)
+#define FHS_ANA_ROTATE 1  // 1: ring slots rotate with the step (loop unrolled over NTAP/2 steps)
 #endif
 
 // Workgroup barrier without a memory fence (the copies are waited for by
@@ -310,8 +310,7 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
   int ph = 0, k = 0;
   // step g at ring rotation S (= g mod H when the loop is unrolled over H
   // steps, else H-1 after a shift of the ring by two)
-  auto step = [&](auto S, int g) __attribute__((always_inline)) {
-    constexpr int s = decltype(S)::value;
+  auto phase_top = [&]() __attribute__((always_inline)) {
     if (k == 0) {
       // the phase's copies were issued before the previous phase's 4P
       // stores, the only later vector-memory operations of this wave; the
@@ -323,6 +322,9 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
       barrier();
       if (ph + 1 < nph) issue_phase(ph + 1);
     }
+  };
+  auto step = [&](auto S, int g) __attribute__((always_inline)) {
+    constexpr int s = decltype(S)::value;
     const float *buf = smem + (ph & 1) * A.lds_buf;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -371,13 +373,18 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
     }
   };
 #if FHS_ANA_ROTATE
-  for (int g0 = 0; g0 < nsteps; g0 += H)
+  // one copy of the phase code, H copies of the step body (one per ring
+  // rotation, selected by g mod H)
+  for (int g = 0, s = 0; g < nsteps; ++g) {
+    phase_top();
     unroll_steps<H>([&](auto S) __attribute__((always_inline)) {
-      const int g = g0 + decltype(S)::value;
-      if (g < nsteps) step(S, g);
+      if (s == decltype(S)::value) step(S, g);
     });
+    s = s + 1 == H ? 0 : s + 1;
+  }
 #else
   for (int g = 0; g < nsteps; ++g) {
+    phase_top();
 #pragma unroll
     for (int m = 0; m + 2 < NTAP; ++m) {
       rl[m] = rl[m + 2];
@@ -512,68 +519,78 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
   }
 }
 
-// Dirac basis: coefficient row = pixel; grid-stride over pixels, 4 in flight.
+// Dirac basis (Sec. 2.3.1: the identity as ninth basis, divided by 3):
+// coefficient row = pixel, an elementwise pass.  Its own launch without LDS
+// (so that many workgroups stay resident), grid-stride over the pixels of the
+// rectangle [ky_begin, ky_end) x [kx_begin, kx_end), E pixels per thread in
+// flight and the next E loaded before the current ones are updated.
 template <int MODE, int LCP>
-__device__ __forceinline__ void dirac(const AnaArgs &A, const AnaBand &B, int wg) {
+__global__ void __launch_bounds__(kDiracThreads) dirac_kernel(AnaArgs A) {
+  constexpr int E = kDiracE;
+  const AnaBand &B = A.b[kBases];
   const int L = A.L, C = A.C, Lc = A.Lc;
   const int tid = threadIdx.x;
   const int lane = tid % LCP, grp = tid / LCP, c = grp % C, kq = grp / C;
-  const bool lv = lane < Lc;
+  const int ppw = blockDim.x / (C * LCP);  // pixels per workgroup and pass
+  const bool lv = lane < Lc && kq < ppw;
   const int p = c * Lc + lane;
   const int chan = lv ? c + lane * C : 0;
-  constexpr int E = 4;
-  // pixels of the rectangle [ky_begin, ky_end) x [kx_begin, kx_end), row-major
   const int rw = B.kx_end - B.kx_begin;
   const bool full = rw == B.in_nx;
   const int64_t npix = static_cast<int64_t>(B.ky_end - B.ky_begin) * rw;
   const int64_t pix_first = static_cast<int64_t>(B.ky_begin) * B.in_nx + B.kx_begin;
-  const int64_t stride = static_cast<int64_t>(B.strips) * A.tkx1;  // strips = Dirac workgroups
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * ppw;
   float thr = 0.0f;
   if (MODE == 1) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
   if (MODE == 2) thr = static_cast<float>(A.mu[c]);
-  for (int64_t pix0 = static_cast<int64_t>(wg) * A.tkx1 + kq; pix0 - kq < npix; pix0 += E * stride) {
-    float v[E], w[E], th[E];
-    int64_t pixe[E];
+  auto pixel = [&](int64_t li) { return full ? pix_first + li : pix_first + (li / rw) * B.in_nx + li % rw; };
+  auto load = [&](int64_t l0, float (&v)[E], float (&w)[E], float (&th)[E]) __attribute__((always_inline)) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int64_t li = pix0 + e * stride;
-      pixe[e] = full ? pix_first + li : pix_first + (li / rw) * B.in_nx + li % rw;
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const bool ok = lv && pix0 + e * stride < npix;
-      const int64_t pix = pixe[e];
+      const int64_t li = l0 + e * stride;
+      const bool ok = lv && li < npix;
+      const int64_t pix = ok ? pixel(li) : 0;
       const int64_t i = B.off[0] + pix;
-      v[e] = ok ? B.in[pix * L + chan] * (1.0f / 3.0f) : 0.0f;
+      v[e] = ok ? B.in[pix * L + chan] : 0.0f;
       w[e] = (ok && MODE == 1) ? A.w[i * L + p] : 0.0f;
       th[e] = (ok && MODE == 1) ? A.theta[c * A.I + i] : 0.0f;
     }
+  };
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * ppw + kq;
+  float v[E], w[E], th[E];
+  load(first, v, w, th);
+  for (int64_t l0 = first; l0 - kq < npix; l0 += E * stride) {
+    float vn[E], wn[E], thn[E];
+    load(l0 + E * stride, vn, wn, thn);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const bool ok = lv && pix0 + e * stride < npix;
-      const int64_t i = B.off[0] + pixe[e];
+      const int64_t li = l0 + e * stride;
+      const bool ok = lv && li < npix;
+      const int64_t i = B.off[0] + (ok ? pixel(li) : 0);
+      const float x3 = v[e] * (1.0f / 3.0f);
       if (MODE == 0) {
-        if (ok) A.w[i * L + p] = v[e];
+        if (ok) A.w[i * L + p] = x3;
       } else if (MODE == 1) {
-        const float wn = shrink<LCP>(ok ? w[e] + v[e] : 0.0f, thr * th[e]);
-        if (ok) A.w[i * L + p] = wn;
+        const float nw = shrink<LCP>(w[e] + x3, thr * th[e]);
+        if (ok) A.w[i * L + p] = nw;
       } else {
-        const float r2 = seg_sum(v[e] * v[e], LCP);
+        const float r2 = seg_sum(x3 * x3, LCP);
         if (ok && lane == 0) A.theta[static_cast<int64_t>(c) * A.I + i] = thr / (sqrtf(r2) + thr);
       }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      v[e] = vn[e];
+      w[e] = wn[e];
+      th[e] = thn[e];
     }
   }
 }
 
-// FIRST: level 1 (reads the cube, also handles the Dirac basis); a separate
-// instantiation so that its launches are timed and profiled on their own.
+// FIRST: level 1 (reads the cube); a separate instantiation so that its
+// launches are profiled on their own.
 template <bool FIRST, int MODE, int LCP, bool DIRECT>
-#ifndef FHS_ANA_WAVES_PER_EU
-#define FHS_ANA_WAVES_PER_EU 4  // register budget: 128 VGPRs (two 512-thread workgroups per CU)
-#endif
-__global__ void __launch_bounds__(FHS_ANA_THREADS) __attribute__((amdgpu_waves_per_eu(FHS_ANA_WAVES_PER_EU)))
-kernel(AnaArgs A) {
-  extern __shared__ float smem[];
+__device__ __forceinline__ void kernel_body(const AnaArgs &A, float *smem) {
   const int id = blockIdx.x;
   if (id < A.nbase_wg) {
 #ifndef FHS_ANA_XCD
@@ -601,27 +618,44 @@ kernel(AnaArgs A) {
       case 6: { const AnaBand B = A.b[6]; if (DIRECT) basis_direct<14, MODE, LCP>(A, B, tile); else basis<14, MODE, LCP>(A, B, tile, smem); } break;
       default: { const AnaBand B = A.b[7]; if (DIRECT) basis_direct<16, MODE, LCP>(A, B, tile); else basis<16, MODE, LCP>(A, B, tile, smem); } break;
     }
-  } else if (FIRST) {
-    dirac<MODE, LCP>(A, A.b[kBases], id - A.nbase_wg);
   }
+}
+
+#ifndef FHS_ANA_WAVES_PER_EU
+#define FHS_ANA_WAVES_PER_EU 4  // register budget of the staged kernel: 128 VGPRs (two 512-thread workgroups per CU)
+#endif
+template <bool FIRST, int MODE, int LCP>
+__global__ void __launch_bounds__(FHS_ANA_THREADS) __attribute__((amdgpu_waves_per_eu(FHS_ANA_WAVES_PER_EU)))
+kernel(AnaArgs A) {
+  extern __shared__ float smem[];
+  kernel_body<FIRST, MODE, LCP, false>(A, smem);
+}
+
+// the LDS-free variant keeps its taps in registers (no waves-per-SIMD target)
+template <bool FIRST, int MODE, int LCP>
+__global__ void __launch_bounds__(FHS_ANA_THREADS) kernel_direct(AnaArgs A) {
+  kernel_body<FIRST, MODE, LCP, true>(A, nullptr);
 }
 
 template <int MODE>
 int launch_mode(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const dim3 grid(static_cast<unsigned>(a.nbase_wg + (first ? a.b[kBases].strips : 0))), block(nthreads);
+  const dim3 grid(static_cast<unsigned>(a.nbase_wg)), block(nthreads);
+  const dim3 dgrid(static_cast<unsigned>(first ? a.b[kBases].strips : 0)), dblock(kDiracThreads);
 #define FHS_ANA_CASE(LCP)                                                                      \
   case LCP:                                                                                    \
+    if (dgrid.x > 0) hipLaunchKernelGGL((dirac_kernel<MODE, LCP>), dgrid, dblock, 0, s, a);    \
+    if (grid.x == 0) break;                                                                    \
     if (a.direct) {                                                                            \
       if (first)                                                                               \
-        hipLaunchKernelGGL((kernel<true, MODE, LCP, true>), grid, block, 0, s, a);             \
+        hipLaunchKernelGGL((kernel_direct<true, MODE, LCP>), grid, block, 0, s, a);             \
       else                                                                                     \
-        hipLaunchKernelGGL((kernel<false, MODE, LCP, true>), grid, block, 0, s, a);            \
+        hipLaunchKernelGGL((kernel_direct<false, MODE, LCP>), grid, block, 0, s, a);            \
     } else {                                                                                   \
       if (first)                                                                               \
-        hipLaunchKernelGGL((kernel<true, MODE, LCP, false>), grid, block, lds, s, a);          \
+        hipLaunchKernelGGL((kernel<true, MODE, LCP>), grid, block, lds, s, a);          \
       else                                                                                     \
-        hipLaunchKernelGGL((kernel<false, MODE, LCP, false>), grid, block, lds, s, a);         \
+        hipLaunchKernelGGL((kernel<false, MODE, LCP>), grid, block, lds, s, a);         \
     }                                                                                          \
     break;
   switch (a.Lcp) {

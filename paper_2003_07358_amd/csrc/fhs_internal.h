@@ -18,6 +18,8 @@ constexpr int kMaxLc = 64;         // channels per sub-cube
 #ifndef FHS_ANA_THREADS
 #define FHS_ANA_THREADS 512        // analysis workgroup size bound (256 or 512)
 #endif
+constexpr int kDiracThreads = 256;  // workgroup size of the Dirac-band kernel
+constexpr int kDiracE = 8;          // pixels per thread in flight there
 constexpr int kAnaLaneSeg = 512;   // LDS words of one staged W row run (TKX L <= threads per workgroup)
 constexpr int kAnaThSeg = 128;     // LDS words of one staged theta segment (C TKX <= threads / 4)
 static_assert(FHS_ANA_THREADS <= kAnaLaneSeg, "analysis W segments hold up to one word per thread");

@@ -35,6 +35,37 @@ namespace fhs {
 
 namespace {
 
+constexpr int kOobS = static_cast<int>(0x80000000u);  // buffer offset past any range: loads 0, stores dropped
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_s(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), static_cast<short>(0), static_cast<int>(bytes),
+                                           0x00020000);
+}
+__device__ __forceinline__ float ld_f32s(__amdgpu_buffer_rsrc_t r, int voff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+__device__ __forceinline__ void st_f32s(float v, __amdgpu_buffer_rsrc_t r, int voff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, 0, 0);
+}
+// Waits until at most n (0, 4, 8, 16) of this wave's vector-memory operations
+// are outstanding (they complete in issue order).
+__device__ __forceinline__ void wait_vm_but_s(int n) {
+  if (n == 4)
+    asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+  else if (n == 8)
+    asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+  else if (n == 16)
+    asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+  else
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+// Workgroup barrier without a memory fence.
+__device__ __forceinline__ void barrier_s() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Segment j of a phase = (row j / 4, band j % 4): copy it into dst + j * segp.
 __device__ __forceinline__ void issue_band_rows(const SynBand &B, int k0, int nrows, int kx0, int segn, int segp,
                                                 int L, float *dst) {
@@ -143,11 +174,29 @@ __device__ __forceinline__ void syn_basis(const SynArgs &A, const SynBand &B, in
   const int off = kq * L + p;
   const int x = 2 * (kx0 + kq);
 
+  // byte offsets of this lane's two output pixels in an output row run that
+  // starts at column 2 kx0, or out of range
+  int vx[2];
+#pragma unroll
+  for (int px = 0; px < 2; ++px)
+    vx[px] = (lv && x + px >= B.x_begin && x + px < B.x_end) ? ((2 * kq + px) * L + p) * 4 : kOobS;
+  auto run = [&](int y) __attribute__((always_inline)) {
+    const bool yv = y >= y0 && y < y1;
+    return rsrc_s(B.out + (yv ? (static_cast<int64_t>(y) * B.nx + 2 * kx0) * L : 0), yv ? 0x7fffffffu : 0u);
+  };
+
   Ring<NTAP> R;
   ring_zero(R);
   issue_band_rows(B, ks, P, kx0, segn, segp, L, smem);
   for (int ph = 0; ph < nph; ++ph) {
-    wait_loads_and_sync();
+    // the phase's copies precede the previous phase's 4P stores, a fixed
+    // four per step (dropped outside the tile), the only later vector-memory
+    // operations of this wave
+    if (ph == 0)
+      wait_vm_but_s(0);
+    else
+      wait_vm_but_s(4 * P);
+    barrier_s();
     if (ph + 1 < nph) issue_band_rows(B, ks + (ph + 1) * P, P, kx0, segn, segp, L, smem + ((ph + 1) & 1) * 4 * P * segp);
     const float *buf = smem + (ph & 1) * 4 * P * segp;
 #pragma unroll
@@ -161,12 +210,14 @@ __device__ __forceinline__ void syn_basis(const SynArgs &A, const SynBand &B, in
           ring_out<NTAP>(R, acc);
 #pragma unroll
           for (int py = 0; py < 2; ++py) {
-            const int y = 2 * kp + py;
+            const __amdgpu_buffer_rsrc_t ro = run(2 * kp + py);
 #pragma unroll
-            for (int px = 0; px < 2; ++px)
-              if (lv && y >= y0 && y < y1 && x + px >= B.x_begin && x + px < B.x_end)
-                B.out[(static_cast<int64_t>(y) * B.nx + x + px) * L + p] = acc[py][px];
+            for (int px = 0; px < 2; ++px) st_f32s(acc[py][px], ro, vx[px]);
           }
+        } else {
+          const __amdgpu_buffer_rsrc_t none = rsrc_s(B.out, 0u);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) st_f32s(0.0f, none, kOobS + 1024 * i);
         }
       }
     }
@@ -263,6 +314,13 @@ struct RingSet<BEND, BEND, P> {
 
 // Bases B0 .. B1-1 of level 1 summed into the image; FIRST also adds the Dirac
 // basis and applies beta, the second group accumulates onto the first.
+//
+// Vector-memory order per phase: the values read at the outputs of the next
+// phase (loaded into registers), then the next phase's band copies, then the
+// phase's output stores, a fixed four per step (range-checked buffer stores;
+// out-of-range lanes and the steps before the first output store nothing).
+// The wait at a phase boundary therefore leaves the previous phase's stores in
+// flight, and the barrier carries no memory fence.
 template <int B0, int B1, bool FIRST, int P>
 __global__ void __launch_bounds__(FHS_SYN_THREADS) __attribute__((amdgpu_waves_per_eu(FHS_FINAL_WPE)))
 syn_final_kernel(SynFinalArgs A) {
@@ -289,28 +347,42 @@ syn_final_kernel(SynFinalArgs A) {
   const int sfirst = -(B1 - 1);
   const int nsteps = nout - sfirst;
   const int nph = (nsteps + P - 1) / P;
+  // byte offsets of this lane's two output pixels in an image row run that
+  // starts at column 2 kx0 (natural order for the image, positions for the
+  // Dirac band), or out of range
+  int vx[2], vd[2];
+#pragma unroll
+  for (int px = 0; px < 2; ++px) {
+    const bool in = lv && x + px >= A.x_begin && x + px < A.x_end;
+    vx[px] = in ? ((2 * kq + px) * L + ch) * 4 : kOobS;
+    vd[px] = in ? ((2 * kq + px) * L + p) * 4 : kOobS;
+  }
+  const int64_t row_floats = static_cast<int64_t>(A.nx) * L;
+  // the image (or Dirac band) row run of output row y, empty outside the tile's rows
+  auto run = [&](const float *base, int y) __attribute__((always_inline)) {
+    const bool yv = y >= y0 && y < y1;
+    return rsrc_s(base + (yv ? static_cast<int64_t>(y) * row_floats + static_cast<int64_t>(2 * kx0) * L : 0),
+                  yv ? 0x7fffffffu : 0u);
+  };
 
   // values read at the outputs of step s: the Dirac coefficient and beta's
   // previous image (first group) or the image of the first group (second)
-  auto pre = [&](int s, float v[2][2], float gv[2][2]) {
-    const int kp = ks + s;
+  auto pre = [&](int s, float v[2][2], float gv[2][2]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int py = 0; py < 2; ++py)
+    for (int py = 0; py < 2; ++py) {
+      const int y = (s >= 0 && s < nout) ? 2 * (ks + s) + py : -1;
+      const __amdgpu_buffer_rsrc_t rx = run(A.x, y);
 #pragma unroll
       for (int px = 0; px < 2; ++px) {
-        const int y = 2 * kp + py;
-        v[py][px] = 0.0f;
-        gv[py][px] = 0.0f;
-        if (s >= 0 && s < nout && lv && y >= y0 && y < y1 && x + px >= A.x_begin && x + px < A.x_end) {
-          const int64_t pix = static_cast<int64_t>(y) * A.nx + x + px;
-          if (FIRST) {
-            v[py][px] = A.dirac[pix * L + p];
-            if (A.beta != 0.0f) gv[py][px] = A.x[pix * L + ch];
-          } else {
-            v[py][px] = A.x[pix * L + ch];
-          }
+        if (FIRST) {
+          v[py][px] = ld_f32s(run(A.dirac, y), vd[px]);
+          gv[py][px] = A.beta != 0.0f ? ld_f32s(rx, vx[px]) : 0.0f;
+        } else {
+          v[py][px] = ld_f32s(rx, vx[px]);
+          gv[py][px] = 0.0f;
         }
       }
+    }
   };
   float vq[P][2][2], gq[P][2][2];
 #pragma unroll
@@ -318,22 +390,37 @@ syn_final_kernel(SynFinalArgs A) {
   R.issue(A, sfirst, ks, kx0, L, smem);
 
   for (int ph = 0; ph < nph; ++ph) {
-    wait_loads_and_sync();
-    if (ph + 1 < nph) R.issue(A, sfirst + (ph + 1) * P, ks, kx0, L, smem + ((ph + 1) & 1) * half);
+    if (ph == 0)
+      wait_vm_but_s(0);
+    else
+      wait_vm_but_s(4 * P);
+    // (the compiler's own wait for the loaded output values: they were
+    // issued before the copies just waited for)
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+      asm volatile("" ::"v"(vq[k][0][0]), "v"(vq[k][0][1]), "v"(vq[k][1][0]), "v"(vq[k][1][1]), "v"(gq[k][0][0]),
+                   "v"(gq[k][0][1]), "v"(gq[k][1][0]), "v"(gq[k][1][1]));
+    barrier_s();
+    float vcur[P][2][2], gcur[P][2][2];
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+#pragma unroll
+      for (int py = 0; py < 2; ++py)
+#pragma unroll
+        for (int px = 0; px < 2; ++px) {
+          vcur[k][py][px] = vq[k][py][px];
+          gcur[k][py][px] = gq[k][py][px];
+        }
+    if (ph + 1 < nph) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) pre(sfirst + (ph + 1) * P + k, vq[k], gq[k]);
+      R.issue(A, sfirst + (ph + 1) * P, ks, kx0, L, smem + ((ph + 1) & 1) * half);
+    }
     const float *buf = smem + (ph & 1) * half;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       const int s = sfirst + ph * P + k;
       if (s < nout) {
-        float vcur[2][2], gcur[2][2];
-#pragma unroll
-        for (int py = 0; py < 2; ++py)
-#pragma unroll
-          for (int px = 0; px < 2; ++px) {
-            vcur[py][px] = vq[k][py][px];
-            gcur[py][px] = gq[k][py][px];
-          }
-        pre(s + P, vq[k], gq[k]);
         R.push(A, s, k, off, L, buf);
         if (s >= 0) {
           float acc[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
@@ -341,20 +428,25 @@ syn_final_kernel(SynFinalArgs A) {
           const int kp = ks + s;
 #pragma unroll
           for (int py = 0; py < 2; ++py) {
-            const int y = 2 * kp + py;
+            const __amdgpu_buffer_rsrc_t rx = run(A.x, 2 * kp + py);
 #pragma unroll
             for (int px = 0; px < 2; ++px) {
-              if (lv && y >= y0 && y < y1 && x + px >= A.x_begin && x + px < A.x_end) {
-                float *dst = A.x + (static_cast<int64_t>(y) * A.nx + x + px) * L + ch;
-                if (FIRST) {
-                  const float v = scale * (acc[py][px] + vcur[py][px]);
-                  *dst = A.beta != 0.0f ? fmaf(A.beta, gcur[py][px], v) : v;
-                } else {
-                  *dst = fmaf(scale, acc[py][px], vcur[py][px]);
-                }
+              float o;
+              if (FIRST) {
+                const float v = scale * (acc[py][px] + vcur[k][py][px]);
+                o = A.beta != 0.0f ? fmaf(A.beta, gcur[k][py][px], v) : v;
+              } else {
+                o = fmaf(scale, acc[py][px], vcur[k][py][px]);
               }
+              st_f32s(o, rx, vx[px]);
             }
           }
+        } else {
+          // (steps before the first output: four dropped stores at distinct,
+          // non-adjacent offsets, which the compiler cannot merge)
+          const __amdgpu_buffer_rsrc_t none = rsrc_s(A.x, 0u);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) st_f32s(0.0f, none, kOobS + 1024 * i);
         }
       }
     }
