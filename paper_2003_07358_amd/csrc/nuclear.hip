@@ -429,11 +429,23 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
 // be long.  Wave w computes channel block w % NB of the row blocks
 // w / NB, w / NB + RW, ... (RW = 4 / NB waves share a block; for NB = 3 the
 // fourth wave idles).
+// Row stride (floats) of the staged X and P segments of nuc_recon1: a row
+// stride that is a multiple of 16 words would put the 16 pixels an MFMA
+// operand reads (same channel) in the same LDS bank, so such strides get four
+// words of padding.
+__host__ __device__ __forceinline__ int recon1_stride(int L) { return L % 16 == 0 ? L + 4 : L; }
+// floats of one staged array (X or P) of S pixels on the 16-byte path: whole
+// 256-float copy chunks
+__host__ __device__ __forceinline__ int recon1_region(int S, int L) {
+  return (S * recon1_stride(L) + 255) / 256 * 256;
+}
+
 template <int NB>
 __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   constexpr int W = NB * 16;
   constexpr int RW = NB >= 4 ? 1 : 4 / NB;
   constexpr int MAXRB = kMaxSeg / 16;  // row blocks per segment, upper bound
+  constexpr int kMaxChunks = 5;        // 16-byte copy chunks per wave and array (ceil(17 / 4))
   extern __shared__ float sm[];
   __shared__ double dsh[2][kMaxSeg];
   const NucGeom &g = A.g;
@@ -443,8 +455,8 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   if (y0 >= F.hy) return;
   const int y1 = min(y0 + A.chunk_wrows, F.hy);
   const int S = A.seg, L = g.L, Lc = g.Lc;
+  const int Lp = recon1_stride(L);
   const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;
-  const int BUF = stage_words(S, L);
   const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const bool active = wave < NB * RW;
   const int mb = wave % NB, rres = wave / NB;
@@ -454,10 +466,52 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   for (int kk = 0; kk < W / 4; ++kk)
     kr[kk] = A.kmat[static_cast<int64_t>(q) * A.lc16 * A.lc16 + (4 * kk + ln / 16) * A.lc16 + 16 * mb + (ln & 15)];
 
-  issue_seg(A, F, seg_of(0, y0, nsx, S, F.hx), sm, dsh[0], true);
+  // Staging: with L a multiple of 4 the X and P runs of a segment (n pixels
+  // x L floats, contiguous in HBM) are copied in 16-byte chunks into rows of
+  // Lp floats; chunk i covers the 4-float groups u = 64 i + lane, row u / (Lp / 4).
+  // The per-lane source offsets do not depend on the segment (rows past its
+  // end fall outside the run and read zero), so each wave computes those of
+  // its chunks i = wave + 4 t once.
+  const bool vec = L % 4 == 0;
+  const int gp = Lp / 4, nchunk = (S * gp + 63) / 64;
+  // X then P, each in whole chunks (the 16-byte path) or S rows of L floats
+  const int preg = vec ? recon1_region(S, L) : S * L;
+  const int BUF = 2 * preg;
+  int coff[kMaxChunks];
+#pragma unroll
+  for (int t = 0; t < kMaxChunks; ++t) {
+    const int u = 64 * (wave + 4 * t) + ln, r = u / gp, gg = u - r * gp;
+    coff[t] = (gg < L / 4 && r < S) ? (r * L + 4 * gg) * 4 : static_cast<int>(0x80000000u);
+  }
+  auto issue = [&](const Seg &sg, float *buf, double *dd) __attribute__((always_inline)) {
+    if (!vec) {
+      issue_seg(A, F, sg, buf, dd, true);
+      return;
+    }
+    const float *xs = A.x + (static_cast<int64_t>(F.wy0 + sg.y) * g.nx + F.wx0 + sg.s0) * L;
+    const float *ps = A.p + F.poff + (static_cast<int64_t>(sg.y) * F.hx + sg.s0) * Lc;
+    const fhs_int32x4 rx = buffer_rsrc(xs, static_cast<unsigned>(sg.n * L * 4));
+    const fhs_int32x4 rp = buffer_rsrc(ps, static_cast<unsigned>(sg.n * L * 4));
+#pragma unroll
+    for (int t = 0; t < kMaxChunks; ++t) {
+      const int i = wave + 4 * t;
+      if (i < nchunk) {
+        fhs_raw_buffer_load_lds(rx, lds_words(buf + 256 * i), 16, coff[t], 0, 0, 0);
+        fhs_raw_buffer_load_lds(rp, lds_words(buf + preg + 256 * i), 16, coff[t], 0, 0, 0);
+      }
+    }
+    if (threadIdx.x < S) {
+      const int i = threadIdx.x;
+      dd[i] = i < sg.n ? ramp(sg.y, F.sy, g.qy, g.oy, F.hy) * ramp(sg.s0 + i, F.sx, g.qx, g.ox, F.hx) : 0.0;
+    }
+  };
+  // (the copy_span path keeps rows of L floats)
+  const int rs = vec ? Lp : L;
+
+  issue(seg_of(0, y0, nsx, S, F.hx), sm, dsh[0]);
   for (int i = 0; i < nseg; ++i) {
     wait_loads_and_sync();
-    if (i + 1 < nseg) issue_seg(A, F, seg_of(i + 1, y0, nsx, S, F.hx), sm + ((i + 1) & 1) * BUF, dsh[(i + 1) & 1], true);
+    if (i + 1 < nseg) issue(seg_of(i + 1, y0, nsx, S, F.hx), sm + ((i + 1) & 1) * BUF, dsh[(i + 1) & 1]);
     float *buf = sm + (i & 1) * BUF;
     const double *d = dsh[i & 1];
     const Seg sg = seg_of(i, y0, nsx, S, F.hx);
@@ -472,7 +526,7 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
         // Z[r][k] = P[r][k] + D_r X[r][k] (one sub-cube: X and P rows have the
         // same layout), read at compile-time offsets from per-row bases
         const bool rv = r < sg.n;
-        const float *xr = buf + r * L + ln / 16, *pr = xr + S * L;
+        const float *xr = buf + r * rs + ln / 16, *pr = xr + preg;
         const double dr = d[r];
         v4d res = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -600,7 +654,8 @@ int launch_nuc_recon(const NucArgs &a, int nspatial, void *stream) {
   const dim3 grid(a.chunks, nspatial);
   if (a.g.C == 1) {
     // (+64 words: masked-out lanes read up to 63 words past a buffer)
-    const size_t lds1 = static_cast<size_t>(2 * 2 * a.seg * a.g.L + 64) * sizeof(float);
+    const int preg = a.g.L % 4 == 0 ? recon1_region(a.seg, a.g.L) : a.seg * a.g.L;
+    const size_t lds1 = static_cast<size_t>(2 * 2 * preg + 64) * sizeof(float);
     switch (a.lc16 / 16) {
       case 1: hipLaunchKernelGGL(nuc_recon1_kernel<1>, grid, dim3(256), lds1, s, a); break;
       case 2: hipLaunchKernelGGL(nuc_recon1_kernel<2>, grid, dim3(256), lds1, s, a); break;
