@@ -19,6 +19,7 @@ constexpr int kMaxDiracWg = 8192;
 #endif
 constexpr int kAnaLdsBytes = FHS_ANA_LDS_KB * 1024;  // LDS budget of an analysis workgroup (two per CU)
 constexpr int kAnaThreads = FHS_ANA_THREADS;          // upper bound on analysis workgroup size
+constexpr int kCUs = 256;                              // compute units of an MI355X
 
 int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
@@ -89,18 +90,6 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     if (nth < 64) return fail(FHS_EUNSUPPORTED, "analysis: fewer than 64 threads per workgroup");
     if (p->C * TKX > kAnaThSeg) return fail(FHS_EUNSUPPORTED, "analysis: more than 128 sub-cube columns per tile");
     const int tab_words = nchunk * 64;
-    a.P = 1;
-    for (int P = p->tune.ana_phase; P >= 1; P /= 2)
-      if ((2 * ana_lds_buf(a, P) + tab_words) * 4 <= kAnaLdsBytes || P == 1) {
-        a.P = P;
-        break;
-      }
-    a.lds_buf = ana_lds_buf(a, a.P);
-    a.lds_wv = 2 * a.P * a.lds_row;
-    a.lds_th = a.lds_wv + 4 * a.P * kAnaLaneSeg;
-    a.lds_tab = 2 * a.lds_buf;
-    a.lds_words = a.lds_tab + tab_words;
-    if (a.lds_words * 4 > 160 * 1024) return fail(FHS_EUNSUPPORTED, "analysis: LDS tile exceeds 160 KB");
     int tmax = 0;
     for (int b = 0; b < kBases; ++b) {
       AnaBand &B = a.b[b];
@@ -124,6 +113,22 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     }
     a.tiles_per_xcd = ceil_div(tmax, 8);
     a.nbase_wg = 64 * a.tiles_per_xcd;
+    // steps per phase: the most up to the tuned value whose double buffer fits
+    // the LDS budget; a launch with no more workgroups than two per CU (the
+    // deeper levels) may take the whole LDS of a CU per workgroup
+    const int budget = a.nbase_wg <= 2 * kCUs ? 160 * 1024 : kAnaLdsBytes;
+    a.P = 1;
+    for (int P = p->tune.ana_phase; P >= 1; P /= 2)
+      if ((2 * ana_lds_buf(a, P) + tab_words) * 4 <= budget || P == 1) {
+        a.P = P;
+        break;
+      }
+    a.lds_buf = ana_lds_buf(a, a.P);
+    a.lds_wv = 2 * a.P * a.lds_row;
+    a.lds_th = a.lds_wv + 4 * a.P * kAnaLaneSeg;
+    a.lds_tab = 2 * a.lds_buf;
+    a.lds_words = a.lds_tab + tab_words;
+    if (a.lds_words * 4 > 160 * 1024) return fail(FHS_EUNSUPPORTED, "analysis: LDS tile exceeds 160 KB");
     if (j == 0) {
       AnaBand &D = a.b[kBases];
       D.in = x;

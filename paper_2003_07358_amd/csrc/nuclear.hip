@@ -554,7 +554,7 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
 // weight and the offset of the pixel's row in each facet's P (sub-cube 0).
 // Then thread t works on channel t % L of pixels t / L, t / L + 256 / L, ...:
 // every P read and the gradient update are coalesced across the channels.
-constexpr int kGatherPx = 64;
+constexpr int kGatherPx = 256;
 
 __global__ void __launch_bounds__(256) nuc_gather_kernel(GatherArgs A) {
   __shared__ double dk[kGatherPx][4];
@@ -592,16 +592,30 @@ __global__ void __launch_bounds__(256) nuc_gather_kernel(GatherArgs A) {
   if (t >= per * L) return;
   const int ch = t % L, c = ch % g.C, l = ch / g.C;
   const float *pc = A.p + c * g.p_sub + l;
-  for (int i = t / L; i < npx; i += per) {
-    float pv[4];
+  float *grow = A.grad + (static_cast<int64_t>(y) * g.nx + x0) * L + ch;
+  // U pixels per thread in flight: all their loads are issued before the first use
+  constexpr int U = 4;
+  for (int i0 = t / L; i0 < npx; i0 += U * per) {
+    float pv[U][4], gv[U];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pv[k] = dk[i][k] != 0.0 ? pc[rk[i][k]] : 0.0f;
-    double sum = 0.0;
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * per;
+      const bool ok = i < npx;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sum += dk[i][k] * static_cast<double>(pv[k]);
-    const float v = static_cast<float>(A.zeta * sum);
-    float *gp = A.grad + (static_cast<int64_t>(y) * g.nx + x0 + i) * L + ch;
-    *gp = A.beta != 0.0f ? fmaf(A.beta, *gp, v) : v;
+      for (int k = 0; k < 4; ++k) pv[u][k] = (ok && dk[ok ? i : 0][k] != 0.0) ? pc[rk[i][k]] : 0.0f;
+      gv[u] = (ok && A.beta != 0.0f) ? grow[static_cast<int64_t>(i) * L] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * per;
+      if (i < npx) {
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sum += dk[i][k] * static_cast<double>(pv[u][k]);
+        const float v = static_cast<float>(A.zeta * sum);
+        grow[static_cast<int64_t>(i) * L] = A.beta != 0.0f ? fmaf(A.beta, gv[u], v) : v;
+      }
+    }
   }
 }
 

@@ -77,7 +77,7 @@ extern "C" int fhs_plan_autotune(fhs_plan *p, const float *xcheck, float *pdual,
     trial(c);
   }
   for (int j = 0; j < p->cfg.levels && j < kMaxLevels; ++j)
-    for (int rows : {16, 32, 64, 128}) {
+    for (int rows : {8, 16, 32, 64, 128}) {
       fhs_tuning c = best;
       c.ana_rows[j] = rows;
       trial(c);
