@@ -322,7 +322,8 @@ struct RingSet<BEND, BEND, P> {
 // The wait at a phase boundary therefore leaves the previous phase's stores in
 // flight, and the barrier carries no memory fence.
 template <int B0, int B1, bool FIRST, int P>
-__global__ void __launch_bounds__(FHS_SYN_THREADS) __attribute__((amdgpu_waves_per_eu(FHS_FINAL_WPE)))
+__global__ void __launch_bounds__(FHS_SYN_THREADS)
+__attribute__((amdgpu_waves_per_eu(B1 - B0 <= 2 ? 2 * FHS_FINAL_WPE : FHS_FINAL_WPE)))
 syn_final_kernel(SynFinalArgs A) {
   extern __shared__ float smem[];
   const int L = A.L, Lcp = A.Lcp, C = A.C, Lc = A.Lc;
@@ -471,14 +472,18 @@ static void launch_final_group(const SynFinalArgs &a, int nthreads, hipStream_t 
     hipLaunchKernelGGL((syn_final_kernel<B0, B1, FIRST, 1>), dim3(nwg), dim3(nthreads), lds, s, a);
 }
 
-// group 0: bases [0, kFinalSplit) + Dirac (applies beta); group 1: the rest.
+// group 0: bases [0, kFinalSplit) + Dirac (applies beta); groups 1 and 2:
+// the rest in two halves (fewer rings per thread: more waves per SIMD).
 int launch_synthesis_final(const SynFinalArgs &a, int nthreads, int group, void *stream) {
   if (a.strips * a.yblocks <= 0) return FHS_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  constexpr int kMid = (kFinalSplit + kBases) / 2;
   if (group == 0)
     launch_final_group<0, kFinalSplit, true>(a, nthreads, s);
+  else if (group == 1)
+    launch_final_group<kFinalSplit, kMid, false>(a, nthreads, s);
   else
-    launch_final_group<kFinalSplit, kBases, false>(a, nthreads, s);
+    launch_final_group<kMid, kBases, false>(a, nthreads, s);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return fail(FHS_EHIP, std::string("final synthesis launch: ") + hipGetErrorString(err));
   return FHS_OK;
