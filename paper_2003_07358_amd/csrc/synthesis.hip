@@ -285,12 +285,6 @@ struct RingSet {
     ring_zero(r);
     next.zero();
   }
-  // rows of steps s0 .. s0+P-1 of this basis into its region of the phase buffer
-  __device__ __forceinline__ void issue(const SynFinalArgs &A, int s0, int ks, int kx0, int L, float *lds) {
-    const int segp = fin_segp(A.tk, b, L);
-    issue_band_rows(A.b[b], ks + s0 + b, P, kx0, (A.tk + b) * L, segp, L, lds);
-    next.issue(A, s0, ks, kx0, L, lds + 4 * P * segp);
-  }
   __device__ __forceinline__ void push(const SynFinalArgs &A, int s, int k, int off, int L, const float *lds) {
     const int segp = fin_segp(A.tk, b, L);
     if (s >= -b) ring_push<2 * (b + 1)>(lds + 4 * k * segp, segp, off, L, r);
@@ -305,7 +299,6 @@ struct RingSet {
 template <int BEND, int P>
 struct RingSet<BEND, BEND, P> {
   __device__ __forceinline__ void zero() {}
-  __device__ __forceinline__ void issue(const SynFinalArgs &, int, int, int, int, float *) {}
   __device__ __forceinline__ void push(const SynFinalArgs &, int, int, int, int, const float *) {}
   __device__ __forceinline__ void out(float[2][2]) {}
 };
@@ -344,6 +337,56 @@ syn_final_kernel(SynFinalArgs A) {
   for (int b = B0; b < B1; ++b) half += 4 * P * fin_segp(A.tk, b, L);
   RingSet<B0, B1, P> R;
   R.zero();
+
+  // Band-row copies: descriptors of the group's bands in LDS (read back as
+  // wave-uniform values when a copy is issued, so that the 4 (B1 - B0) band
+  // addresses do not occupy scalar registers across the loop), and the copy
+  // work of a phase spread over the waves as (basis, row, band) tasks.
+  constexpr int NB = B1 - B0;
+  __shared__ uint64_t dsc_base[NB][4];       // byte address of row 0 at column kx0
+  __shared__ uint32_t dsc_rec[NB], dsc_row[NB];  // bytes from column kx0 to the row end; bytes per row
+  __shared__ int dsc_ky[NB], dsc_off[NB];    // rows; offset of the basis' region in a phase buffer (floats)
+  if (tid < 4 * NB) {
+#pragma unroll
+    for (int bb = B0; bb < B1; ++bb)
+      if ((tid >> 2) == bb - B0) {
+        const SynBand &S = A.b[bb];
+        const int band = tid & 3;
+        const float *src = band == 0 ? S.ll : band == 1 ? S.lh : band == 2 ? S.hl : S.hh;
+        dsc_base[bb - B0][band] = reinterpret_cast<uint64_t>(src + static_cast<int64_t>(kx0) * L);
+        if (band == 0) {
+          dsc_rec[bb - B0] = static_cast<uint32_t>(max(0, S.Kx - kx0)) * L * 4;
+          dsc_row[bb - B0] = static_cast<uint32_t>(S.Kx) * L * 4;
+          dsc_ky[bb - B0] = S.Ky;
+          int o = 0;
+          for (int b2 = B0; b2 < bb; ++b2) o += 4 * P * fin_segp(A.tk, b2, L);
+          dsc_off[bb - B0] = o;
+        }
+      }
+  }
+  __syncthreads();
+  const int wv = wave_id(), nwv = full_wave_count(), ln = tid & 63;
+  auto issue = [&](int s0, float *lds) __attribute__((always_inline)) {
+    for (int t = wv; t < NB * 4 * P && wv < nwv; t += nwv) {
+      const int bi = t / (4 * P), rem = t - bi * 4 * P, row = rem >> 2, band = rem & 3;
+      const int b = B0 + bi;
+      const int k = ks + s0 + b + row;  // coefficient row
+      const int ky = __builtin_amdgcn_readfirstlane(dsc_ky[bi]);
+      const bool kv = k >= 0 && k < ky;
+      const uint64_t base = dsc_base[bi][band];
+      const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(base));
+      const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(base >> 32));
+      const uint32_t rowb = __builtin_amdgcn_readfirstlane(dsc_row[bi]);
+      const uint32_t rec = __builtin_amdgcn_readfirstlane(dsc_rec[bi]);
+      const char *rp = reinterpret_cast<const char *>((static_cast<uint64_t>(hi) << 32) | lo) +
+                       (kv ? static_cast<uint64_t>(k) * rowb : 0);
+      const fhs_int32x4 rs = buffer_rsrc(rp, kv ? rec : 0u);
+      const int segn = (A.tk + b) * L, segp = round_up(segn, 64);
+      float *dst = lds + __builtin_amdgcn_readfirstlane(dsc_off[bi]) + (4 * row + band) * segp;
+      for (int j = 0; j < segn; j += 64)
+        fhs_raw_buffer_load_lds(rs, lds_words(dst + j), 4, (j + ln) * 4, 0, 0, 0);
+    }
+  };
   const float scale = A.alpha * (1.0f / 3.0f);
   const int sfirst = -(B1 - 1);
   const int nsteps = nout - sfirst;
@@ -388,7 +431,7 @@ syn_final_kernel(SynFinalArgs A) {
   float vq[P][2][2], gq[P][2][2];
 #pragma unroll
   for (int k = 0; k < P; ++k) pre(sfirst + k, vq[k], gq[k]);
-  R.issue(A, sfirst, ks, kx0, L, smem);
+  issue(sfirst, smem);
 
   for (int ph = 0; ph < nph; ++ph) {
     if (ph == 0)
@@ -415,7 +458,7 @@ syn_final_kernel(SynFinalArgs A) {
     if (ph + 1 < nph) {
 #pragma unroll
       for (int k = 0; k < P; ++k) pre(sfirst + (ph + 1) * P + k, vq[k], gq[k]);
-      R.issue(A, sfirst + (ph + 1) * P, ks, kx0, L, smem + ((ph + 1) & 1) * half);
+      issue(sfirst + (ph + 1) * P, smem + ((ph + 1) & 1) * half);
     }
     const float *buf = smem + (ph & 1) * half;
 #pragma unroll
