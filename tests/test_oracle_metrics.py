@@ -35,7 +35,7 @@ def test_snr_log_tends_to_snr_for_a_large_noise_level():
     # log10(z / eps + 1) = z / (eps ln 10) + O(z^2 / eps^2): the ratio of norms
     # tends to the linear one as eps grows
     r = cube(3)
-    x = r + 0.05 * np.random.default_rng(4).standard_normal(r.shape)
+    x = r * np.exp(0.05 * np.random.default_rng(4).standard_normal(r.shape))  # positive, like the iterates
     lin = metrics.snr(r, x)
     np.testing.assert_allclose(metrics.snr_log(r, x, np.full(4, 1e6)), lin, rtol=1e-4)
     assert not np.allclose(metrics.snr_log(r, x, np.full(4, 1e-3)), lin, rtol=1e-2)
