@@ -246,6 +246,18 @@ int fhs_reweight(const fhs_plan *plan, const float *x, const double *upsilon,
 int fhs_pdfb_closure(const fhs_plan *plan, float *x, float *xcheck, float *v, const float *y,
                      const double *eps, const float *grad, double tau, double *xi, void *stream);
 
+/* Reconstruction quality (Sec. 4.2), per channel l of the plan's cube:
+ *   snr[l]     = 20 log10(||x_ref_l||_2 / ||x_ref_l - x_l||_2)
+ *   snr_log[l] = the same on log10(z / eps_l + 1) of both images (term-wise)
+ * in dB, +inf where the estimate equals the reference.  x_ref, x: float32
+ * [ny][nx][L] (natural channel order), device; eps: float64 [L] device noise
+ * levels, or NULL to skip the log-scale metric (then snr_log may be NULL);
+ * snr, snr_log: float64 [L] device outputs.  Sums in float64, fixed order
+ * (bitwise reproducible).  Images must be non-negative where the log-scale
+ * metric is taken (otherwise it is NaN).  Uses the plan's workspace. */
+int fhs_snr(const fhs_plan *plan, const float *x_ref, const float *x, const double *eps, double *snr,
+            double *snr_log, void *stream);
+
 /* Everything one PDFB iteration touches (device pointers, caller-owned). */
 typedef struct {
   float *x;                 /* X [ny][nx][L]                                    */

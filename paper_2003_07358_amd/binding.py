@@ -75,6 +75,7 @@ SYMBOLS = {
                                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "fhs_reweight": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_snr": (ctypes.c_int, [ctypes.c_void_p] * 7),
     "fhs_pdfb_closure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                         ctypes.c_void_p, ctypes.c_void_p]),
@@ -313,6 +314,20 @@ class Plan:
             self._t(v, n, torch.float32, "v"), self._t(y, n, torch.float32, "y"),
             self._t(eps, self.L, torch.float64, "eps"), self._t(grad, n, torch.float32, "grad"), float(tau),
             self._t(xi, 1, torch.float64, "xi"), _stream(x)))
+
+    def snr(self, x_ref, x, eps=None):
+        """Per-channel reconstruction SNR in dB (float64 device tensor [L]) and,
+        with noise levels eps (float64 [L]), the log-scale SNR (else None)."""
+        import torch
+        self._need_ws()
+        n = self.sizes["n_x"]
+        out = torch.empty(self.L, dtype=torch.float64, device=x.device)
+        out_log = torch.empty(self.L, dtype=torch.float64, device=x.device) if eps is not None else None
+        _check(self._lib.fhs_snr(
+            self._p, self._t(x_ref, n, torch.float32, "x_ref"), self._t(x, n, torch.float32, "x"),
+            self._t(eps, self.L, torch.float64, "eps") if eps is not None else None, self._t(out, self.L, torch.float64, "snr"),
+            self._t(out_log, self.L, torch.float64, "snr_log") if out_log is not None else None, _stream(x)))
+        return out, out_log
 
     def pdfb_state(self, x, xcheck, p, w, v, y, eps, theta, theta_bar, mu, mu_bar, grad, xi, zeta=1.0,
                    kappa=1.0, tau=0.33):

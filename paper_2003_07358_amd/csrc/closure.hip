@@ -135,6 +135,64 @@ __global__ void __launch_bounds__(kThreads) closure_xi(ClosureArgs a) {
   }
 }
 
+// Reconstruction metrics (Sec. 4.2): per block and channel the four sums
+// sum r^2, sum (r - x)^2 and, with noise levels, the same of
+// a = log10(r / eps + 1), b = log10(x / eps + 1); then one block sums the
+// partials in a fixed order and writes 10 log10(num / den) per channel.
+__global__ void __launch_bounds__(kThreads) snr_part(SnrArgs a) {
+  __shared__ double sh[4][kThreads];
+  const int t = threadIdx.x;
+  const int L = a.L, G = kThreads / L;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * a.ppb;
+  const int64_t p1 = min(p0 + a.ppb, a.npix);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (t < G * L) {
+    const int g = t / L, l = t - (t / L) * L;
+    const double eps = a.eps ? a.eps[l] : 1.0;
+    for (int64_t p = p0 + g; p < p1; p += G) {
+      const int64_t e = p * L + l;
+      const double r = a.ref[e], x = a.x[e];
+      s[0] += r * r;
+      s[1] += (r - x) * (r - x);
+      if (a.eps) {
+        const double lr = log10(r / eps + 1.0), lx = log10(x / eps + 1.0);
+        s[2] += lr * lr;
+        s[3] += (lr - lx) * (lr - lx);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sh[k][t] = s[k];
+  __syncthreads();
+  if (t < L)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.part[(static_cast<int64_t>(blockIdx.x) * 4 + k) * L + t] = group_sum(sh[k], G, L, t);
+}
+
+__device__ __forceinline__ double db(double num, double den) {
+  return den > 0.0 ? 10.0 * log10(num / den) : __builtin_huge_val();
+}
+
+__global__ void __launch_bounds__(kThreads) snr_final(SnrArgs a) {
+  __shared__ double sh[4][kThreads];
+  const int t = threadIdx.x;
+  const int L = a.L, G = kThreads / L;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (t < G * L) {
+    const int g = t / L, l = t - (t / L) * L;
+    for (int b = g; b < a.nblocks; b += G)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s[k] += a.part[(static_cast<int64_t>(b) * 4 + k) * L + l];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sh[k][t] = s[k];
+  __syncthreads();
+  if (t < L) {
+    a.snr[t] = db(group_sum(sh[0], G, L, t), group_sum(sh[1], G, L, t));
+    if (a.eps) a.snr_log[t] = db(group_sum(sh[2], G, L, t), group_sum(sh[3], G, L, t));
+  }
+}
+
 int check(const char *what) {
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return fail(FHS_EHIP, std::string(what) + ": " + hipGetErrorString(err));
@@ -142,6 +200,15 @@ int check(const char *what) {
 }
 
 }  // namespace
+
+int launch_snr(const SnrArgs &a, void *stream) {
+  if (a.L < 1 || a.L > kThreads) return fail(FHS_EUNSUPPORTED, "snr: channels must be in [1, 256]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(snr_part, dim3(static_cast<unsigned>(a.nblocks)), dim3(kThreads), 0, s, a);
+  if (int rc = check("snr_part")) return rc;
+  hipLaunchKernelGGL(snr_final, dim3(1), dim3(kThreads), 0, s, a);
+  return check("snr_final");
+}
 
 int launch_closure(const ClosureArgs &a, void *stream) {
   if (a.L < 1 || a.L > kThreads) return fail(FHS_EUNSUPPORTED, "closure: channels must be in [1, 256]");

@@ -152,6 +152,15 @@ struct ClosureArgs {
   int L, nblocks;
 };
 
+struct SnrArgs {
+  const float *ref, *x;  // [N][L] reference and estimate
+  const double *eps;     // [L] noise levels for the log-scale metric, or null
+  double *part;          // [nblocks][4][L] block partial sums (workspace)
+  double *snr, *snr_log; // [L] outputs (snr_log written only with eps)
+  int64_t npix, ppb;
+  int L, nblocks;
+};
+
 // ---------------------------------------------------------------- launchers
 int launch_analysis(const AnaArgs &a, int nthreads, bool first, void *stream);
 int launch_analysis_m0(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
@@ -164,6 +173,7 @@ int launch_nuc_eig(const NucArgs &a, int nfacets, void *stream);
 int launch_nuc_recon(const NucArgs &a, int nspatial, void *stream);
 int launch_nuc_gather(const GatherArgs &a, void *stream);
 int launch_closure(const ClosureArgs &a, void *stream);
+int launch_snr(const SnrArgs &a, void *stream);
 
 }  // namespace fhs
 

@@ -61,6 +61,26 @@ int fhs_pdfb_closure(const fhs_plan *p, float *x, float *xcheck, float *v, const
   return closure(p, x, xcheck, v, y, eps, grad, tau, xi, stream);
 }
 
+int fhs_snr(const fhs_plan *p, const float *x_ref, const float *x, const double *eps, double *snr, double *snr_log,
+            void *stream) {
+  if (!p) return fail(FHS_EINVAL, "null plan");
+  if (!p->ws) return fail(FHS_ENOWORKSPACE, "no workspace attached (fhs_plan_set_workspace)");
+  if (!x_ref || !x || !snr) return fail(FHS_EINVAL, "fhs_snr: null array");
+  if (eps && !snr_log) return fail(FHS_EINVAL, "fhs_snr: snr_log is required with eps");
+  SnrArgs a{};
+  a.ref = x_ref;
+  a.x = x;
+  a.eps = eps;
+  a.part = reinterpret_cast<double *>(static_cast<char *>(p->ws) + p->ws_red);
+  a.snr = snr;
+  a.snr_log = snr_log;
+  a.npix = static_cast<int64_t>(p->cfg.ny) * p->cfg.nx;
+  a.ppb = p->red_ppb;
+  a.L = p->L;
+  a.nblocks = p->red_blocks;
+  return launch_snr(a, stream);
+}
+
 int fhs_pdfb_iteration(const fhs_plan *p, const fhs_pdfb_state *s, int32_t iter, void *stream) {
   if (int rc = check_state(s)) return rc;
   if (iter < 0) return fail(FHS_EINVAL, "iteration index must be >= 0");

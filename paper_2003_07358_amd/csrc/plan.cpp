@@ -240,7 +240,8 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
     p->red_blocks = static_cast<int>((npix + p->red_ppb - 1) / p->red_ppb);
   }
   p->ws_red = ws;
-  ws = align256(ws + static_cast<int64_t>(p->red_blocks) * std::max(p->L, 2) * 8);
+  // (closure: one or two sums per channel and block; metrics: four)
+  ws = align256(ws + static_cast<int64_t>(p->red_blocks) * std::max(4 * p->L, 2) * 8);
   p->ws_factor = ws;
   ws = align256(ws + static_cast<int64_t>(p->L) * 8);
   p->ws_bytes = ws;

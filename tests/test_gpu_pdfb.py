@@ -150,3 +150,25 @@ def test_pdfb_graph_replays_match_eager():
         log(f"    replay {rep}: identical")
     graph.close()
     assert np.isfinite(eager["xi"]).all() and (eager["xi"] > 0).all()
+
+
+@pytest.mark.parametrize("L,with_log", [(20, True), (5, True), (64, False)])
+def test_snr_matches_oracle(L, with_log):
+    """Reconstruction SNR and log-scale SNR per channel (Sec. 4.2) against the
+    oracle: the same float32 images, sums in float64 on both sides."""
+    from oracle import metrics
+    ny, nx = 37, 53
+    plan = fhs.Plan(ny, nx, L, 1, 1, 1, 0, 0, 2).attach_workspace()
+    rng = np.random.default_rng(11 + L)
+    ref = rng.uniform(0.0, 3.0, (ny, nx, L)).astype(np.float32)
+    est = (ref * np.exp(0.1 * rng.standard_normal(ref.shape))).astype(np.float32)
+    est[0, 0, :] = ref[0, 0, :]
+    eps = rng.uniform(0.01, 0.5, L)
+    d_eps = torch.from_numpy(eps).cuda() if with_log else None
+    snr, snr_log = plan.snr(torch.from_numpy(ref).cuda(), torch.from_numpy(est).cuda(), d_eps)
+    np.testing.assert_allclose(snr.cpu().numpy(), metrics.snr(ref, est), rtol=1e-10)
+    if with_log:
+        np.testing.assert_allclose(snr_log.cpu().numpy(), metrics.snr_log(ref, est, eps), rtol=1e-10)
+    # exact estimate -> +inf
+    same, _ = plan.snr(torch.from_numpy(ref).cuda(), torch.from_numpy(ref).cuda())
+    assert np.all(np.isinf(same.cpu().numpy()))
