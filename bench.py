@@ -31,9 +31,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(plan, w, kernel):
+def kernel_bytes(plan, w, kernel, fused=True):
     """Algorithmic HBM bytes of all launches of `kernel` in one step: every
-    input the kernel must read and every output it must write, once."""
+    input the kernel must read and every output it must write, once.  fused:
+    the Dirac band's dual update runs in the first level-1 synthesis group
+    (the batched step), else in the level-1 analysis (the per-facet form)."""
     bands = plan.bands()
     N, L, C, lev = w.ny * w.nx, w.L, w.C, w.levels
     per_basis = 3 * lev + 1
@@ -47,12 +49,18 @@ def kernel_bytes(plan, w, kernel):
             r = band_rows(b, 1)
             tot += 3 * r * (2 * L * 4 + C * 4)            # details: W read + write, theta
             tot += r * L * 4 * (2 if lev == 1 else 1)     # low-low: W rw (1 level) or written once
-        tot += N * (2 * L * 4 + C * 4)                    # Dirac: W rw, theta
+        if not fused:
+            tot += N * (2 * L * 4 + C * 4)                # Dirac: W rw, theta
         return tot, 1
     if kernel in ("synth_final_a", "synth_final_b"):
         bs = range(0, 4) if kernel == "synth_final_a" else range(4, 8)
         tot = sum(4 * band_rows(b, 1) * L * 4 for b in bs)
-        tot += N * L * 4 * (2 if kernel == "synth_final_a" else 2)   # Dirac + G write / G read + write
+        if kernel == "synth_final_a":
+            tot += N * L * 4 * 2                          # Dirac W read + G write
+            if fused:
+                tot += N * (2 * L * 4 + C * 4)            # Xcheck, Dirac W write, theta
+        else:
+            tot += N * L * 4 * 2                          # G read + write
         return tot, 1
     raise ValueError(kernel)
 
@@ -208,7 +216,7 @@ def main():
     plan.profile(None)
     voxels = w.voxels
     value = voxels / (ms / 1e3)
-    kb, per_step = kernel_bytes(plan, w, args.kernel)
+    kb, per_step = kernel_bytes(plan, w, args.kernel, fused=args.form == "batched")
     avg_launch_s = (kms / launches) / 1e3 if launches else float("nan")
     achieved = kb / per_step / avg_launch_s / 1e9
     traffic = traffic_from_profiles(args.kernel, w.name)

@@ -55,7 +55,7 @@ int ana_lds_buf(const AnaArgs &a, int P) {
 }
 
 int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, const double *mu, double inv_kappa,
-                 int mode, void *stream, int fy = -1, int fx = -1, int level = -1) {
+                 int mode, void *stream, int fy = -1, int fx = -1, int level = -1, bool with_dirac = true) {
   int tkx1, nth;
   if (int rc = thread_cfg(p, &tkx1, &nth, kAnaThreads)) return rc;
   const int TKX = tkx1;
@@ -143,7 +143,9 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       // grid-stride workgroups of the Dirac-band kernel (kDiracE pixels in flight per thread)
       const int64_t npix = static_cast<int64_t>(D.ky_end - D.ky_begin) * (D.kx_end - D.kx_begin);
       const int ppw = kDiracThreads / (p->C * p->Lcp);
-      D.strips = npix > 0 ? std::max(1, std::min(kMaxDiracWg, ceil_div(npix, static_cast<int64_t>(kDiracE) * ppw))) : 0;
+      D.strips = npix > 0 && with_dirac
+                     ? std::max(1, std::min(kMaxDiracWg, ceil_div(npix, static_cast<int64_t>(kDiracE) * ppw)))
+                     : 0;
     }
     const int kid = j == 0 ? FHS_K_ANALYSIS_L1 : FHS_K_ANALYSIS;
     prof_begin(p, kid, stream);
@@ -160,8 +162,11 @@ int syn_strips(int b, int e, int tk) { return e > b ? ceil_div((e - 1) / 2 - b /
 // x = beta x + alpha Psi w.  Facet (fy, fx) >= 0 restricts the outputs to the
 // samples that facet owns, level >= 0 to one level (0 = the final level-1
 // pass): the per-facet execution form.
+// xin non-null: the level-1 pass also performs the Dirac band's l21 dual
+// update (left out of the analysis) with input xin, weights theta, mu, 1/kappa.
 int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, float beta, void *stream, int fy = -1,
-                  int fx = -1, int level = -1) {
+                  int fx = -1, int level = -1, const float *xin = nullptr, const float *theta = nullptr,
+                  const double *mu = nullptr, double inv_kappa = 0.0) {
   int tk, nth;
   if (int rc = thread_cfg(p, &tk, &nth, FHS_SYN_THREADS)) return rc;
   const int L = p->L, levels = p->cfg.levels;
@@ -220,8 +225,15 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
     B.nx = p->cfg.nx;
     B.ntap = p->ntap[b];
   }
-  f.dirac = w + dirac_off(p) * L;
+  f.dirac = const_cast<float *>(w) + dirac_off(p) * L;
   f.x = x;
+  f.xin = xin;
+  f.theta = theta;
+  f.mu = mu;
+  f.inv_kappa = inv_kappa;
+  f.I = p->I;
+  f.dirac_row = dirac_off(p);
+  f.theta_bytes = static_cast<int64_t>(p->C) * p->I * 4;
   f.alpha = alpha;
   f.beta = beta;
   f.ny = p->cfg.ny;
@@ -364,8 +376,11 @@ int fhs_l21_dual_update(const fhs_plan *p, const float *xcheck, float *w, const 
   if (int rc = check_plan(p)) return rc;
   if (!xcheck || !w || !theta || !mu || !grad) return fail(FHS_EINVAL, "fhs_l21_dual_update: null array");
   if (!(kappa > 0)) return fail(FHS_EINVAL, "kappa must be positive");
-  if (int rc = run_analysis(p, xcheck, w, const_cast<float *>(theta), mu, 1.0 / kappa, 1, stream)) return rc;
-  return run_synthesis(p, w, grad, static_cast<float>(kappa), beta, stream);
+  // (the Dirac band's dual update runs inside the level-1 synthesis, which
+  // reads the updated coefficient right away)
+  if (int rc = run_analysis(p, xcheck, w, const_cast<float *>(theta), mu, 1.0 / kappa, 1, stream, -1, -1, -1, false))
+    return rc;
+  return run_synthesis(p, w, grad, static_cast<float>(kappa), beta, stream, -1, -1, -1, xcheck, theta, mu, 1.0 / kappa);
 }
 
 int fhs_nuclear_dual_update(const fhs_plan *p, const float *xcheck, float *pdual, const double *theta_bar,

@@ -571,7 +571,7 @@ __global__ void __launch_bounds__(kDiracThreads) dirac_kernel(AnaArgs A) {
       if (MODE == 0) {
         if (ok) A.w[i * L + p] = x3;
       } else if (MODE == 1) {
-        const float nw = shrink<LCP>(w[e] + x3, thr * th[e]);
+        const float nw = l21_row_update(w[e], v[e], thr * th[e], LCP);
         if (ok) A.w[i * L + p] = nw;
       } else {
         const float r2 = seg_sum(x3 * x3, LCP);

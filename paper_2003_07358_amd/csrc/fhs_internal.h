@@ -95,8 +95,16 @@ struct SynArgs {
 // accumulated into the image: x = beta x + alpha / 3 (sum_b ... + w_dirac).
 struct SynFinalArgs {
   SynBand b[kBases];          // out, strips, yblocks unused per basis
-  const float *dirac;         // [ny][nx][L] (positions)
+  float *dirac;               // [ny][nx][L] (positions); updated in place when fused
   float *x;                   // [ny][nx][L] natural channel order
+  // fused Dirac-band dual update (first group): W_d <- shrink(W_d + xin / 3)
+  // before W_d enters the output; null xin: W_d is read as it is
+  const float *xin;           // [ny][nx][L] natural channel order
+  const float *theta;         // [C][I] weights (the Dirac rows at dirac_row)
+  const double *mu;           // [C]
+  double inv_kappa;
+  int64_t I, dirac_row;       // coefficient rows per sub-cube; first row of the Dirac band
+  int64_t theta_bytes;        // C * I * 4 (< 2^31)
   float alpha, beta;
   int ny, nx, L, Lcp, C, Lc, tk, ty, strips, yblocks;
   int y_begin, y_end, x_begin, x_end;  // output pixels computed (all unless per facet)

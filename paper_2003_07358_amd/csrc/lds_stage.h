@@ -106,4 +106,16 @@ __device__ __forceinline__ float seg_sum(float v, int lcp) {
   return v;
 }
 
+// The l21 row update of one coefficient held by a lane of an lcp-lane segment
+// (the segment holds the row over a sub-cube's channels): u = w + v/3, then
+// u min(1, thr_th / ||u||). Products are never contracted into the adds, so
+// that every kernel applying it (the analysis' Dirac pass and the level-1
+// synthesis that fuses it) produces the same bits.
+__device__ __forceinline__ float l21_row_update(float w, float v, float thr_th, int lcp) {
+#pragma clang fp contract(off)
+  const float u = w + v * (1.0f / 3.0f);
+  const float r2 = seg_sum(u * u, lcp);
+  return u * fminf(1.0f, thr_th * __frsqrt_rn(r2));
+}
+
 }  // namespace fhs

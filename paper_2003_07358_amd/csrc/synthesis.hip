@@ -409,18 +409,46 @@ syn_final_kernel(SynFinalArgs A) {
                   yv ? 0x7fffffffu : 0u);
   };
 
+  // Fused Dirac-band dual update (first group, when xin is given): the
+  // Dirac coefficient of an output pixel is updated here, W_d <- W_d + xin / 3
+  // shrunk by its l2 row norm over the sub-cube's channels (the analysis'
+  // Dirac arithmetic, operation for operation), stored, and enters the output.
+  const bool fuse = FIRST && A.xin != nullptr;
+  const float thr = fuse ? static_cast<float>(A.mu[c] * A.inv_kappa) : 0.0f;
+  // theta word of this lane's two pixels in a row run starting at column 2 kx0
+  int vt[2];
+#pragma unroll
+  for (int px = 0; px < 2; ++px)
+    vt[px] = vd[px] != kOobS ? static_cast<int>((static_cast<int64_t>(c) * A.I + A.dirac_row + 2 * kx0 + 2 * kq + px) * 4)
+                             : kOobS;
+  // theta of output row y (empty outside the tile's rows); soffset: the row
+  auto trow = [&](int y, int &so) __attribute__((always_inline)) {
+    const bool yv = fuse && y >= y0 && y < y1;
+    so = yv ? static_cast<int>(static_cast<int64_t>(y) * A.nx * 4) : 0;
+    return rsrc_s(A.theta, yv ? static_cast<uint32_t>(A.theta_bytes) : 0u);
+  };
+  const int stores = fuse ? 8 : 4;  // per step, fixed (the phase wait counts them)
+
   // values read at the outputs of step s: the Dirac coefficient and beta's
-  // previous image (first group) or the image of the first group (second)
-  auto pre = [&](int s, float v[2][2], float gv[2][2]) __attribute__((always_inline)) {
+  // previous image (first group; fused: also the analysis input and theta) or
+  // the image of the first group (second)
+  auto pre = [&](int s, float v[2][2], float gv[2][2], float xv[2][2], float tv[2][2]) __attribute__((always_inline)) {
 #pragma unroll
     for (int py = 0; py < 2; ++py) {
       const int y = (s >= 0 && s < nout) ? 2 * (ks + s) + py : -1;
       const __amdgpu_buffer_rsrc_t rx = run(A.x, y);
+      int so = 0;
+      const __amdgpu_buffer_rsrc_t rt = trow(y, so);
 #pragma unroll
       for (int px = 0; px < 2; ++px) {
+        xv[py][px] = tv[py][px] = 0.0f;
         if (FIRST) {
           v[py][px] = ld_f32s(run(A.dirac, y), vd[px]);
           gv[py][px] = A.beta != 0.0f ? ld_f32s(rx, vx[px]) : 0.0f;
+          if (fuse) {
+            xv[py][px] = ld_f32s(run(A.xin, y), vx[px]);
+            tv[py][px] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rt, vt[px], so, 0));
+          }
         } else {
           v[py][px] = ld_f32s(rx, vx[px]);
           gv[py][px] = 0.0f;
@@ -428,24 +456,27 @@ syn_final_kernel(SynFinalArgs A) {
       }
     }
   };
-  float vq[P][2][2], gq[P][2][2];
+  float vq[P][2][2], gq[P][2][2], xq[P][2][2], tq[P][2][2];
 #pragma unroll
-  for (int k = 0; k < P; ++k) pre(sfirst + k, vq[k], gq[k]);
+  for (int k = 0; k < P; ++k) pre(sfirst + k, vq[k], gq[k], xq[k], tq[k]);
   issue(sfirst, smem);
 
   for (int ph = 0; ph < nph; ++ph) {
     if (ph == 0)
       wait_vm_but_s(0);
     else
-      wait_vm_but_s(4 * P);
+      wait_vm_but_s(stores * P);
     // (the compiler's own wait for the loaded output values: they were
     // issued before the copies just waited for)
 #pragma unroll
-    for (int k = 0; k < P; ++k)
+    for (int k = 0; k < P; ++k) {
       asm volatile("" ::"v"(vq[k][0][0]), "v"(vq[k][0][1]), "v"(vq[k][1][0]), "v"(vq[k][1][1]), "v"(gq[k][0][0]),
                    "v"(gq[k][0][1]), "v"(gq[k][1][0]), "v"(gq[k][1][1]));
+      asm volatile("" ::"v"(xq[k][0][0]), "v"(xq[k][0][1]), "v"(xq[k][1][0]), "v"(xq[k][1][1]), "v"(tq[k][0][0]),
+                   "v"(tq[k][0][1]), "v"(tq[k][1][0]), "v"(tq[k][1][1]));
+    }
     barrier_s();
-    float vcur[P][2][2], gcur[P][2][2];
+    float vcur[P][2][2], gcur[P][2][2], xcur[P][2][2], tcur[P][2][2];
 #pragma unroll
     for (int k = 0; k < P; ++k)
 #pragma unroll
@@ -454,10 +485,12 @@ syn_final_kernel(SynFinalArgs A) {
         for (int px = 0; px < 2; ++px) {
           vcur[k][py][px] = vq[k][py][px];
           gcur[k][py][px] = gq[k][py][px];
+          xcur[k][py][px] = xq[k][py][px];
+          tcur[k][py][px] = tq[k][py][px];
         }
     if (ph + 1 < nph) {
 #pragma unroll
-      for (int k = 0; k < P; ++k) pre(sfirst + (ph + 1) * P + k, vq[k], gq[k]);
+      for (int k = 0; k < P; ++k) pre(sfirst + (ph + 1) * P + k, vq[k], gq[k], xq[k], tq[k]);
       issue(sfirst + (ph + 1) * P, smem + ((ph + 1) & 1) * half);
     }
     const float *buf = smem + (ph & 1) * half;
@@ -473,11 +506,20 @@ syn_final_kernel(SynFinalArgs A) {
 #pragma unroll
           for (int py = 0; py < 2; ++py) {
             const __amdgpu_buffer_rsrc_t rx = run(A.x, 2 * kp + py);
+            float wd[2] = {vcur[k][py][0], vcur[k][py][1]};
+            if (fuse) {
+              const __amdgpu_buffer_rsrc_t rd = run(A.dirac, 2 * kp + py);
+#pragma unroll
+              for (int px = 0; px < 2; ++px) {
+                wd[px] = l21_row_update(vcur[k][py][px], xcur[k][py][px], thr * tcur[k][py][px], Lcp);
+                st_f32s(wd[px], rd, vd[px]);
+              }
+            }
 #pragma unroll
             for (int px = 0; px < 2; ++px) {
               float o;
               if (FIRST) {
-                const float v = scale * (acc[py][px] + vcur[k][py][px]);
+                const float v = scale * (acc[py][px] + wd[px]);
                 o = A.beta != 0.0f ? fmaf(A.beta, gcur[k][py][px], v) : v;
               } else {
                 o = fmaf(scale, acc[py][px], vcur[k][py][px]);
@@ -486,11 +528,14 @@ syn_final_kernel(SynFinalArgs A) {
             }
           }
         } else {
-          // (steps before the first output: four dropped stores at distinct,
+          // (steps before the first output: dropped stores at distinct,
           // non-adjacent offsets, which the compiler cannot merge)
           const __amdgpu_buffer_rsrc_t none = rsrc_s(A.x, 0u);
 #pragma unroll
           for (int i = 0; i < 4; ++i) st_f32s(0.0f, none, kOobS + 1024 * i);
+          if (fuse)
+#pragma unroll
+            for (int i = 4; i < 8; ++i) st_f32s(0.0f, none, kOobS + 1024 * i);
         }
       }
     }
