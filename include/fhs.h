@@ -292,6 +292,54 @@ int fhs_pdfb_graph_create(const fhs_plan *plan, const fhs_pdfb_state *state, int
 int fhs_graph_launch(const fhs_graph *graph, void *stream);
 void fhs_graph_destroy(fhs_graph *graph);
 
+/* ---------------------------------------------------------------- reweighting solve */
+
+/* Stopping parameters of the outer reweighting loop (Alg. 1) and of each
+ * PDFB run inside it (Alg. 2).  The paper's values: max_reweights 5,
+ * min_iter 10, max_iter 2000, rw_tol = pdfb_tol = 1e-5, res_factor 1.01. */
+typedef struct {
+  int32_t max_reweights; /* T: at most this many PDFB runs                       */
+  double rw_tol;         /* the loop ends once ||X(t+1)-X(t)||/||X(t)|| <= rw_tol */
+  int32_t min_iter;      /* PDFB iterations always performed                    */
+  int32_t max_iter;      /* PDFB iteration cap (>= 1 and >= min_iter)           */
+  double pdfb_tol;       /* bound on the relative variation xi of the iterate   */
+  double res_factor;     /* residual bound ||r|| <= res_factor ||eps||          */
+} fhs_solve_params;
+
+typedef struct {
+  int32_t runs;          /* PDFB runs performed (reweighting passes)            */
+  int64_t iterations;    /* PDFB iterations over all runs                       */
+  double rw_xi;          /* relative variation of the last run (+inf: X(t) = 0) */
+  double last_xi;        /* xi of the last iteration                            */
+  double last_res;       /* ||r|| tested after the last iteration               */
+} fhs_solve_report;
+
+/* Algorithm 1 with the identity as measurement operator, every array
+ * resident on the device:
+ *   t = 0, xi = +inf
+ *   while t < max_reweights and xi > rw_tol:
+ *     theta, theta_bar <- weights from X (as fhs_reweight, with upsilon [C]
+ *                         and upsilon_bar [C*Q], float64 device arrays)
+ *     X(t) <- X (kept in x_prev), Xcheck <- X
+ *     PDFB run (fhs_pdfb_iteration, iteration p writing state->xi[p]) while
+ *       p < min_iter, or p < max_iter and (xi_p > pdfb_tol or
+ *       ||r|| > res_factor ||eps||), where ||r||^2 = sum_l ||y_l - x_l||^2 for
+ *       the iterate entering the last iteration (Alg. 2, residual step)
+ *     xi <- ||X - X(t)||_F / ||X(t)||_F,  t <- t + 1
+ * P, W and v are warm-started from one run to the next (they are never
+ * reset).  All spectral sub-cubes advance together; the stopping quantities
+ * are taken over the whole cube.  state->theta and state->theta_bar are
+ * overwritten (they must be writable device memory), state->xi must hold
+ * max_iter float64, x_prev is a float32 device array of the cube's size.
+ * The loop decides on the host: every iteration ends with a small
+ * device-to-host copy (xi and the per-channel residual sums) and a
+ * synchronization of `stream`.  iters (host, max_reweights int32, or NULL)
+ * receives the iteration count of each run; report (host, or NULL) the
+ * summary.  Uses the plan's workspace. */
+int fhs_reweighting_solve(const fhs_plan *plan, const fhs_pdfb_state *state, const double *upsilon,
+                          const double *upsilon_bar, float *x_prev, const fhs_solve_params *params,
+                          int32_t *iters, fhs_solve_report *report, void *stream);
+
 /* ---------------------------------------------------------------- diagnostics */
 
 /* Kernel identifiers for fhs_plan_profile. */

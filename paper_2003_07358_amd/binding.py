@@ -40,6 +40,16 @@ class _PdfbState(ctypes.Structure):
                [(n, ctypes.c_double) for n in ("zeta", "kappa", "tau")]
 
 
+class _SolveParams(ctypes.Structure):
+    _fields_ = [("max_reweights", ctypes.c_int32), ("rw_tol", ctypes.c_double), ("min_iter", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("pdfb_tol", ctypes.c_double), ("res_factor", ctypes.c_double)]
+
+
+class _SolveReport(ctypes.Structure):
+    _fields_ = [("runs", ctypes.c_int32), ("iterations", ctypes.c_int64), ("rw_xi", ctypes.c_double),
+                ("last_xi", ctypes.c_double), ("last_res", ctypes.c_double)]
+
+
 SYMBOLS = {
     "fhs_version": (ctypes.c_int, []),
     "fhs_last_error": (ctypes.c_char_p, []),
@@ -81,6 +91,10 @@ SYMBOLS = {
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "fhs_pdfb_iteration": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_PdfbState), ctypes.c_int32,
                                           ctypes.c_void_p]),
+    "fhs_reweighting_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_PdfbState), ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_SolveParams),
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_SolveReport),
+                                             ctypes.c_void_p]),
     "fhs_pdfb_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_PdfbState), ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_void_p)]),
     "fhs_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -358,6 +372,28 @@ class Plan:
         import torch
         _check(self._lib.fhs_pdfb_iteration(self._p, ctypes.byref(state), int(it),
                                             ctypes.c_void_p(torch.cuda.current_stream(state.device).cuda_stream)))
+
+    def reweighting_solve(self, state, upsilon, upsilon_bar, x_prev, max_reweights=5, rw_tol=1e-5, min_iter=10,
+                          max_iter=2000, pdfb_tol=1e-5, res_factor=1.01):
+        """Alg. 1 (fhs_reweighting_solve) on a pdfb_state whose theta and
+        theta_bar tensors it overwrites; xi must hold max_iter entries.
+        Returns dict(runs, iterations, iters (per run), rw_xi, last_xi, last_res)."""
+        import torch
+        self._need_ws()
+        if max_iter > state.n_xi:
+            raise FhsError("xi must hold max_iter entries")
+        s = self.sizes
+        prm = _SolveParams(int(max_reweights), float(rw_tol), int(min_iter), int(max_iter), float(pdfb_tol),
+                           float(res_factor))
+        iters = (ctypes.c_int32 * max(1, int(max_reweights)))()
+        rep = _SolveReport()
+        _check(self._lib.fhs_reweighting_solve(
+            self._p, ctypes.byref(state), self._t(upsilon, self.C, torch.float64, "upsilon"),
+            self._t(upsilon_bar, s["n_facets"], torch.float64, "upsilon_bar"),
+            self._t(x_prev, s["n_x"], torch.float32, "x_prev"), ctypes.byref(prm), iters, ctypes.byref(rep),
+            ctypes.c_void_p(torch.cuda.current_stream(state.device).cuda_stream)))
+        return dict(runs=rep.runs, iterations=rep.iterations, iters=list(iters)[:rep.runs], rw_xi=rep.rw_xi,
+                    last_xi=rep.last_xi, last_res=rep.last_res)
 
     def pdfb_graph(self, state, n_iter):
         """HIP graph of n_iter iterations (xi[0 .. n_iter-1])."""

@@ -188,7 +188,12 @@ __global__ void __launch_bounds__(kThreads) snr_final(SnrArgs a) {
   for (int k = 0; k < 4; ++k) sh[k][t] = s[k];
   __syncthreads();
   if (t < L) {
-    a.snr[t] = db(group_sum(sh[0], G, L, t), group_sum(sh[1], G, L, t));
+    const double s0 = group_sum(sh[0], G, L, t), s1 = group_sum(sh[1], G, L, t);
+    if (a.snr) a.snr[t] = db(s0, s1);
+    if (a.sums) {
+      a.sums[t] = s0;
+      a.sums[L + t] = s1;
+    }
     if (a.eps) a.snr_log[t] = db(group_sum(sh[2], G, L, t), group_sum(sh[3], G, L, t));
   }
 }

@@ -164,7 +164,8 @@ struct SnrArgs {
   const float *ref, *x;  // [N][L] reference and estimate
   const double *eps;     // [L] noise levels for the log-scale metric, or null
   double *part;          // [nblocks][4][L] block partial sums (workspace)
-  double *snr, *snr_log; // [L] outputs (snr_log written only with eps)
+  double *snr, *snr_log; // [L] outputs, or null (snr_log written only with eps)
+  double *sums;          // [2][L] raw sums of r^2 and (r - x)^2 per channel, or null
   int64_t npix, ppb;
   int L, nblocks;
 };
@@ -210,7 +211,7 @@ struct fhs_plan {
   int ntap[fhs::kBases];
   // workspace layout (bytes)
   int64_t ws_ll[fhs::kBases][fhs::kMaxLevels];
-  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_red = 0, ws_factor = 0, ws_bytes = 0;
+  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_red = 0, ws_factor = 0, ws_ctl = 0, ws_bytes = 0;
   int64_t red_ppb = 0;                     // closure: pixels per block
   int red_blocks = 0;                      // closure: blocks
   int gram_chunks = 0, max_rows = 0;       // Gram partial slots per facet (workspace capacity)

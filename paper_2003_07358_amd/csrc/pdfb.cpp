@@ -4,6 +4,10 @@
 // so that many iterations replay with one launch.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <limits>
+#include <vector>
+
 #include "fhs_internal.h"
 
 using namespace fhs;
@@ -48,6 +52,25 @@ int check_state(const fhs_pdfb_state *s) {
   return FHS_OK;
 }
 
+// Per-channel sums of r^2 and (r - x)^2 into the workspace's control slot,
+// then copied to host `out` [2L] (synchronizes `stream`).
+int channel_sums(const fhs_plan *p, const float *r, const float *x, double *out, hipStream_t stream) {
+  SnrArgs a{};
+  a.ref = r;
+  a.x = x;
+  a.part = reinterpret_cast<double *>(static_cast<char *>(p->ws) + p->ws_red);
+  a.sums = reinterpret_cast<double *>(static_cast<char *>(p->ws) + p->ws_ctl);
+  a.npix = static_cast<int64_t>(p->cfg.ny) * p->cfg.nx;
+  a.ppb = p->red_ppb;
+  a.L = p->L;
+  a.nblocks = p->red_blocks;
+  if (int rc = launch_snr(a, stream)) return rc;
+  if (hipMemcpyAsync(out, a.sums, sizeof(double) * 2 * p->L, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return fail(FHS_EHIP, "reweighting solve: reading back channel sums failed");
+  return FHS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -88,6 +111,72 @@ int fhs_pdfb_iteration(const fhs_plan *p, const fhs_pdfb_state *s, int32_t iter,
                                    s->kappa, s->grad, stream))
     return rc;
   return closure(p, s->x, s->xcheck, s->v, s->y, s->eps, s->grad, s->tau, s->xi + iter, stream);
+}
+
+int fhs_reweighting_solve(const fhs_plan *p, const fhs_pdfb_state *s, const double *upsilon,
+                          const double *upsilon_bar, float *x_prev, const fhs_solve_params *prm, int32_t *iters,
+                          fhs_solve_report *report, void *stream) {
+  if (!p) return fail(FHS_EINVAL, "null plan");
+  if (!p->ws) return fail(FHS_ENOWORKSPACE, "no workspace attached (fhs_plan_set_workspace)");
+  if (int rc = check_state(s)) return rc;
+  if (!upsilon || !upsilon_bar || !x_prev || !prm) return fail(FHS_EINVAL, "fhs_reweighting_solve: null argument");
+  if (prm->max_reweights < 0 || prm->min_iter < 0 || prm->max_iter < 1 || prm->max_iter < prm->min_iter)
+    return fail(FHS_EINVAL, "reweighting solve: need max_reweights >= 0 and 1 <= max_iter, min_iter <= max_iter");
+  if (!(prm->rw_tol >= 0) || !(prm->pdfb_tol >= 0) || !(prm->res_factor > 0))
+    return fail(FHS_EINVAL, "reweighting solve: tolerances must be >= 0 and res_factor > 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int L = p->L;
+  const size_t cube_bytes = static_cast<size_t>(p->cfg.ny) * p->cfg.nx * L * sizeof(float);
+  std::vector<double> h(2 * static_cast<size_t>(L));
+  // ||eps||
+  if (hipMemcpyAsync(h.data(), s->eps, sizeof(double) * L, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(FHS_EHIP, "reweighting solve: reading eps failed");
+  double eps2 = 0.0;
+  for (int l = 0; l < L; ++l) eps2 += h[l] * h[l];
+  const double res_bound = prm->res_factor * std::sqrt(eps2);
+  auto sum_of = [&](int k) {
+    double v = 0.0;
+    for (int l = 0; l < L; ++l) v += h[static_cast<size_t>(k) * L + l];
+    return v;
+  };
+  float *theta = const_cast<float *>(s->theta);
+  double *theta_bar = const_cast<double *>(s->theta_bar);
+  fhs_solve_report rep{0, 0, std::numeric_limits<double>::infinity(), std::numeric_limits<double>::infinity(),
+                       std::numeric_limits<double>::infinity()};
+  double rw_xi = std::numeric_limits<double>::infinity();
+  for (int t = 0; t < prm->max_reweights && rw_xi > prm->rw_tol; ++t) {
+    if (int rc = fhs_reweight(p, s->x, upsilon, upsilon_bar, theta, theta_bar, stream)) return rc;
+    if (hipMemcpyAsync(x_prev, s->x, cube_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(s->xcheck, s->x, cube_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return fail(FHS_EHIP, "reweighting solve: device copy failed");
+    // Alg. 2 from X(t): r of the iterate entering each iteration
+    if (int rc = channel_sums(p, s->y, s->x, h.data(), st)) return rc;
+    double res = std::sqrt(sum_of(1)), xi = std::numeric_limits<double>::infinity();
+    int32_t it = 0;
+    while (it < prm->min_iter || (it < prm->max_iter && (xi > prm->pdfb_tol || res > res_bound))) {
+      if (it > 0)
+        if (int rc = channel_sums(p, s->y, s->x, h.data(), st)) return rc;
+      res = std::sqrt(sum_of(1));
+      if (int rc = fhs_pdfb_iteration(p, s, it, stream)) return rc;
+      if (hipMemcpyAsync(&xi, s->xi + it, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return fail(FHS_EHIP, "reweighting solve: reading xi failed");
+      ++it;
+    }
+    if (iters) iters[t] = it;
+    rep.iterations += it;
+    rep.last_xi = xi;
+    rep.last_res = res;
+    // relative variation between reweights
+    if (int rc = channel_sums(p, x_prev, s->x, h.data(), st)) return rc;
+    const double n0 = sum_of(0);
+    rw_xi = n0 > 0.0 ? std::sqrt(sum_of(1) / n0) : std::numeric_limits<double>::infinity();
+    rep.runs = t + 1;
+  }
+  rep.rw_xi = rw_xi;
+  if (report) *report = rep;
+  return FHS_OK;
 }
 
 int fhs_pdfb_graph_create(const fhs_plan *p, const fhs_pdfb_state *s, int32_t n_iter, fhs_graph **out) {

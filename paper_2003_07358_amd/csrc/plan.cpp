@@ -244,6 +244,9 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   ws = align256(ws + static_cast<int64_t>(p->red_blocks) * std::max(4 * p->L, 2) * 8);
   p->ws_factor = ws;
   ws = align256(ws + static_cast<int64_t>(p->L) * 8);
+  // per-channel sums read back by the reweighting solve
+  p->ws_ctl = ws;
+  ws = align256(ws + static_cast<int64_t>(p->L) * 2 * 8);
   p->ws_bytes = ws;
   *out = p;
   return FHS_OK;

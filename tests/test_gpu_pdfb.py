@@ -152,6 +152,63 @@ def test_pdfb_graph_replays_match_eager():
     assert np.isfinite(eager["xi"]).all() and (eager["xi"] > 0).all()
 
 
+SOLVE_CASES = {
+    # (case, x0, T, rw_tol, p_min, p_max, pdfb_tol, res_factor): runs that stop
+    # on the relative variation, on the residual, and at the caps; the
+    # deciding values are far from the bounds (checked on the oracle side)
+    "xi_stop": ("q2x2_c2_64x64x12", "zero", 2, 0.0, 2, 12, 0.1, 1.01),
+    "res_stop": ("q3x2_c1_90x70x8", "zero", 2, 0.0, 2, 12, 1.0, 1.01),
+    "caps": ("q3x2_c1_90x70x8", "data", 2, 0.0, 2, 3, 0.0, 1.01),
+    "outer_stop": ("q2x2_c2_64x64x12", "data", 3, 1.0, 1, 2, 0.0, 1.01),
+}
+
+
+@pytest.mark.parametrize("name", list(SOLVE_CASES))
+def test_reweighting_solve_parity(name):
+    """Alg. 1 on the GPU (fhs_reweighting_solve) against the oracle's loop:
+    the same number of runs and iterations per run, and the state after K
+    iterations in all within K * 1e-5 (as for K plain iterations), the weights
+    of the last pass included."""
+    from oracle import solve
+    case, start, T, rw_tol, p_min, p_max, pdfb_tol, res_factor = SOLVE_CASES[name]
+    log(f"[case] reweighting solve {name}: {case} from {start}")
+    pb, y, eps, x0 = pdfb_problem(**PDFB_CASES[case])
+    if start == "zero":
+        x0 = np.zeros_like(x0)
+    kw = dict(T=T, xi_rw=rw_tol, p_min=p_min, p_max=p_max, xi_tol=pdfb_tol, res_factor=res_factor)
+    x, P, W, v, th, thb, rep = solve.reweighting_solve(x0, pb.P, pb.W, np.zeros(x0.shape), y, eps, pb.mu, pb.mu_bar,
+                                                       pb.mu, pb.mu_bar, pb.geom, C=pb.C, levels=pb.levels, **kw)
+    iters = [len(h) for h in rep["runs"]]
+    # every stopping decision of the oracle is taken with a wide margin
+    bound = res_factor * np.linalg.norm(eps)
+    for h in rep["runs"]:
+        for xi, r in h:
+            assert pdfb_tol == 0.0 or np.isinf(xi) or abs(xi / pdfb_tol - 1.0) > 0.05
+            assert abs(r / bound - 1.0) > 0.01
+    assert all(rw_tol == 0.0 or np.isinf(xi) or abs(xi / rw_tol - 1.0) > 0.05 for xi in rep["xi"])
+    log(f"    oracle: iterations per run {iters}, outer xi {rep['xi']}")
+
+    plan = fhs.Plan(*pb.cfg).attach_workspace()
+    t, st = gpu_state(plan, pb, y, eps, x0, p_max)
+    x_prev = torch.empty(x0.size, dtype=torch.float32, device="cuda")
+    got = plan.reweighting_solve(st, dev(pb.mu), dev(pb.mu_bar_flat()), x_prev, max_reweights=T, rw_tol=rw_tol,
+                                 min_iter=p_min, max_iter=p_max, pdfb_tol=pdfb_tol, res_factor=res_factor)
+    log(f"    gpu:    iterations per run {got['iters']}, outer xi {got['rw_xi']:.6e}")
+    assert got["iters"] == iters and got["runs"] == len(iters) and got["iterations"] == sum(iters)
+    K = sum(iters)
+    ref = {"x": x, "p": np.concatenate([q.reshape(-1) for row in P for q in row]), "w": np.concatenate(W, axis=1),
+           "theta": np.concatenate(th), "theta_bar": np.concatenate([q for row in thb for q in row])}
+    for n, r in ref.items():
+        e = rel_l2(host(t[n]).reshape(-1), r.reshape(-1))
+        log(f"    {n}: rel err={e:.3e}")
+        assert e <= K * 1e-5, (n, e)
+    ev = np.linalg.norm(host(t["v"]).reshape(-1) - v.reshape(-1)) / np.linalg.norm(y)
+    log(f"    v: err / ||y|| = {ev:.3e}")
+    assert ev <= K * 1e-5
+    xo = rep["xi"][-1]
+    assert (np.isinf(xo) and np.isinf(got["rw_xi"])) or abs(got["rw_xi"] - xo) <= 1e-3 * xo
+
+
 @pytest.mark.parametrize("L,with_log", [(20, True), (5, True), (64, False)])
 def test_snr_matches_oracle(L, with_log):
     """Reconstruction SNR and log-scale SNR per channel (Sec. 4.2) against the
