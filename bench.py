@@ -80,7 +80,8 @@ def traffic_from_profiles(kernel, workload):
         return None
     d = json.load(open(path))
     from paper_2003_07358_amd.profiling import source_hash
-    if d.get("source_hash") != source_hash():
+    files = d.get("sources")
+    if d.get("source_hash") != source_hash(None if files in (None, "all") else files):
         return None
     return d.get("hbm_bytes_per_launch")
 

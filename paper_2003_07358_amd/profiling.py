@@ -4,6 +4,7 @@
         per-kernel launch count and durations from a --kernel-trace run
     python -m paper_2003_07358_amd.profiling traffic --fetch DIR --write DIR
             --kernel REGEX --calib REGEX --calib-bytes B --name NAME --out FILE --command CMD
+            [--sources KERNEL]
         HBM bytes per launch of the kernels matching REGEX from two --pmc runs
         (FETCH_SIZE, WRITE_SIZE), each scaled by the reading of a reference
         copy kernel that moves a known number of bytes
@@ -33,13 +34,22 @@ def _code_only(text):
     return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
 
 
-def source_hash():
+# the sources that define each profiled kernel and its launch
+KERNEL_SOURCES = {
+    "analysis_l1": ("analysis_impl.h", "analysis_m1.hip", "analysis.cpp", "lds_stage.h", "fhs_internal.h",
+                    "abi.cpp", "plan.cpp"),
+}
+
+
+def source_hash(files=None):
+    """Hash of the code (comments and blank lines left out) of `files` in the
+    kernel source folder, all sources if None."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".cpp", ".h")):
-            with open(os.path.join(CSRC, f)) as fh:
-                h.update(f.encode())
-                h.update(_code_only(fh.read()).encode())
+    names = sorted(files) if files else sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    for f in names:
+        with open(os.path.join(CSRC, f)) as fh:
+            h.update(f.encode())
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -110,8 +120,9 @@ def cmd_stats(a):
 
 
 def cmd_traffic(a):
-    res = {"name": a.name, "source_hash": source_hash(), "command": a.command, "kernel_regex": a.kernel,
-           "calib_regex": a.calib, "calib_bytes": a.calib_bytes}
+    files = KERNEL_SOURCES.get(a.sources) if a.sources else None
+    res = {"name": a.name, "sources": list(files) if files else "all", "source_hash": source_hash(files),
+           "command": a.command, "kernel_regex": a.kernel, "calib_regex": a.calib, "calib_bytes": a.calib_bytes}
     total = 0.0
     for key, d, counter in (("fetch", a.fetch, "FETCH_SIZE"), ("write", a.write, "WRITE_SIZE")):
         agg = counter_per_dispatch(d, counter)
@@ -150,6 +161,7 @@ def main(argv=None):
     t.add_argument("--name", required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--command", default="")
+    t.add_argument("--sources", default="", help="kernel whose source list the hash covers (default: all)")
     a = ap.parse_args(argv)
     (cmd_stats if a.cmd == "stats" else cmd_traffic)(a)
 
