@@ -145,6 +145,7 @@ typedef struct {
   int32_t nuc_chunk_rows;  /* window rows per nuclear workgroup (>= the plan's minimum) */
   int32_t concurrent;      /* 1: the nuclear chain runs on a second stream beside the wavelet chain */
   int32_t ana_direct;      /* 1: analysis loads taps, W and theta straight into registers (no LDS) */
+  int32_t fin_waves;       /* wavefronts per level-1 synthesis workgroup (4, 6 or 8) */
 } fhs_tuning;
 
 /* Current launch shapes (defaults after fhs_plan_create). HOST pointer. */

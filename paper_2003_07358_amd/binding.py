@@ -31,7 +31,8 @@ class _Sizes(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("ana_rows", ctypes.c_int32 * 6)] + [(n, ctypes.c_int32) for n in
-                ("ana_phase", "syn_rows", "fin_rows", "nuc_seg", "nuc_chunk_rows", "concurrent", "ana_direct")]
+                ("ana_phase", "syn_rows", "fin_rows", "nuc_seg", "nuc_chunk_rows", "concurrent", "ana_direct",
+                 "fin_waves")]
 
 
 class _PdfbState(ctypes.Structure):

@@ -26,12 +26,33 @@ int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 float *ws_f(const fhs_plan *p, int64_t off) { return reinterpret_cast<float *>(static_cast<char *>(p->ws) + off); }
 double *ws_d(const fhs_plan *p, int64_t off) { return reinterpret_cast<double *>(static_cast<char *>(p->ws) + off); }
 
-int thread_cfg(const fhs_plan *p, int *tkx1, int *nthreads, int max_threads = 256) {
-  const int per = p->Lcp * p->C;
+bool dense_width_h(int lcp) { return (lcp & (lcp - 1)) != 0; }
+bool dense_lanes(const fhs_plan *p) { return dense_width_h(p->Lcp); }
+int pow2_lanes(const fhs_plan *p) {  // the padded segment width of the plan's L_c
+  int lcp = 4;
+  while (lcp < p->Lc) lcp *= 2;
+  return lcp;
+}
+
+// Coefficient columns per workgroup (each C segments of lcp lanes) and the
+// workgroup size.  Dense widths: 64 / lcp whole segments per wave.
+int thread_cfg_w(int lcp, int C, int *tkx1, int *nthreads, int max_threads) {
+  if (dense_width_h(lcp)) {
+    const int g = 64 / lcp, segs = (max_threads / 64) * g;
+    if (segs < C) return fail(FHS_EUNSUPPORTED, "sub-cubes exceed the lane segments of a workgroup");
+    *tkx1 = segs / C;
+    *nthreads = (*tkx1 * C + g - 1) / g * 64;
+    return FHS_OK;
+  }
+  const int per = lcp * C;
   if (per > 256) return fail(FHS_EUNSUPPORTED, "sub-cubes x padded channels per sub-cube exceed 256");
   *tkx1 = std::max(1, max_threads / per);
   *nthreads = *tkx1 * per;
   return FHS_OK;
+}
+
+int thread_cfg(const fhs_plan *p, int *tkx1, int *nthreads, int max_threads = 256) {
+  return thread_cfg_w(p->Lcp, p->C, tkx1, nthreads, max_threads);
 }
 
 int check_plan(const fhs_plan *p) {
@@ -83,7 +104,10 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     // (plus one pad column per sub-cube block when there are several), in
     // whole copy chunks (256 words with 16-byte copies, else 64)
     a.vec4 = (p->L % 4 == 0 && p->Lc % 4 == 0) ? 1 : 0;
-    const int cw = a.vec4 ? 256 : 64;
+    // (the kernel copies 4 bytes per lane from the natural-order cube when
+    // there are several sub-cubes: a sub-cube's channels are not contiguous)
+    const bool v4 = a.vec4 && (p->C == 1 || j > 0);
+    const int cw = v4 ? 256 : 64;
     const int ncp = 2 * TKX + kMaxTap - 2 + (p->C > 1 ? 1 : 0);
     const int nchunk = ceil_div(static_cast<int64_t>(p->C) * ncp * p->Lcp, cw);
     a.lds_row = nchunk * cw;
@@ -142,7 +166,8 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       D.kx_end = facet ? p->tx[fx + 1] : p->cfg.nx;
       // grid-stride workgroups of the Dirac-band kernel (kDiracE pixels in flight per thread)
       const int64_t npix = static_cast<int64_t>(D.ky_end - D.ky_begin) * (D.kx_end - D.kx_begin);
-      const int ppw = kDiracThreads / (p->C * p->Lcp);
+      const int ppw = kDiracThreads / (p->C * pow2_lanes(p));  // (padded segments)
+      if (ppw < 1) return fail(FHS_EUNSUPPORTED, "Dirac band: sub-cubes exceed the lane segments of a workgroup");
       D.strips = npix > 0 && with_dirac
                      ? std::max(1, std::min(kMaxDiracWg, ceil_div(npix, static_cast<int64_t>(kDiracE) * ppw)))
                      : 0;
@@ -211,6 +236,10 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
     if (rc) return rc;
   }
   if (level > 0) return FHS_OK;
+  // level 1: its own workgroup size (fin_waves) and padded lane segments
+  // (measured faster there than the dense ones)
+  const int lcp_fin = pow2_lanes(p);
+  if (int rc = thread_cfg_w(lcp_fin, p->C, &tk, &nth, 64 * p->tune.fin_waves)) return rc;
   SynFinalArgs f;
   std::memset(&f, 0, sizeof(f));
   for (int b = 0; b < kBases; ++b) {
@@ -239,7 +268,7 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
   f.ny = p->cfg.ny;
   f.nx = p->cfg.nx;
   f.L = L;
-  f.Lcp = p->Lcp;
+  f.Lcp = lcp_fin;
   f.C = p->C;
   f.Lc = p->Lc;
   f.tk = tk;

@@ -177,14 +177,19 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
   if (tile >= B.strips * B.yblocks) return;
   const int L = A.L, C = A.C, Lc = A.Lc, P = A.P;
   const int tid = threadIdx.x;
-  const int lane = tid % LCP, grp = tid / LCP, c = grp % C, kq = grp / C;
-  const int p = c * Lc + lane;
+  int lane, grp;
+  bool idle;
+  seg_map(tid, LCP, lane, grp, idle);
   const int TKX = A.tkx1;
+  // (segments past the tile's TKX columns, possible with dense widths, work
+  // on column 0 and store nothing)
+  const int c = grp % C, kq = grp / C < TKX ? grp / C : 0;
+  const int p = c * Lc + lane;
   const int strip = tile % B.strips, yb = tile / B.strips;
   const int kx0 = B.kx_begin + strip * TKX, ky0 = B.ky_begin + yb * A.tky;
   const int ky1 = min(ky0 + A.tky, B.ky_end);
   const int nkx = min(TKX, B.kx_end - kx0);     // coefficient columns of the tile
-  const bool ok = lane < Lc && kq < nkx;
+  const bool ok = !idle && lane < Lc && grp / C < nkx;
   const int NC = 2 * TKX + NTAP - 2;            // input columns of a staged row
   const int NCP = NC + (C > 1 ? 1 : 0);         // columns per sub-cube block (one pad column spreads the
                                                 // sub-cube blocks over the LDS banks)
@@ -408,11 +413,14 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
   if (tile >= B.strips * B.yblocks) return;
   const int L = A.L, C = A.C, Lc = A.Lc;
   const int tid = threadIdx.x;
-  const int lane = tid % LCP, grp = tid / LCP, c = grp % C, kq = grp / C;
-  const bool lv = lane < Lc;
+  int lane, grp;
+  bool idle;
+  seg_map(tid, LCP, lane, grp, idle);
+  const int TKX = A.tkx1;
+  const int c = grp % C, kq = grp / C < TKX ? grp / C : 0;
+  const bool lv = !idle && lane < Lc && grp / C < TKX;
   const int p = c * Lc + lane;
   const int chan = lv ? (B.in_natural ? c + lane * C : p) : 0;
-  const int TKX = A.tkx1;
   const int strip = tile % B.strips, yb = tile / B.strips;
   const int kx0 = B.kx_begin + strip * TKX, ky0 = B.ky_begin + yb * A.tky;
   const int ky1 = min(ky0 + A.tky, B.ky_end);
@@ -530,9 +538,13 @@ __global__ void __launch_bounds__(kDiracThreads) dirac_kernel(AnaArgs A) {
   const AnaBand &B = A.b[kBases];
   const int L = A.L, C = A.C, Lc = A.Lc;
   const int tid = threadIdx.x;
-  const int lane = tid % LCP, grp = tid / LCP, c = grp % C, kq = grp / C;
-  const int ppw = blockDim.x / (C * LCP);  // pixels per workgroup and pass
-  const bool lv = lane < Lc && kq < ppw;
+  int lane, grp;
+  bool idle;
+  seg_map(tid, LCP, lane, grp, idle);
+  const int c = grp % C, kq = grp / C;
+  // pixels per workgroup and pass
+  const int ppw = dense_width(LCP) ? dense_segments(blockDim.x, LCP) / C : blockDim.x / (C * LCP);
+  const bool lv = !idle && lane < Lc && kq < ppw;
   const int p = c * Lc + lane;
   const int chan = lv ? c + lane * C : 0;
   const int rw = B.kx_end - B.kx_begin;
@@ -642,9 +654,11 @@ int launch_mode(const AnaArgs &a, int nthreads, bool first, size_t lds, void *st
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(static_cast<unsigned>(a.nbase_wg)), block(nthreads);
   const dim3 dgrid(static_cast<unsigned>(first ? a.b[kBases].strips : 0)), dblock(kDiracThreads);
-#define FHS_ANA_CASE(LCP)                                                                      \
+// (the Dirac band always runs on padded segments, DLCP: the level-1
+// synthesis, which fuses its update in the batched step, uses those too)
+#define FHS_ANA_CASE2(LCP, DLCP)                                                               \
   case LCP:                                                                                    \
-    if (dgrid.x > 0) hipLaunchKernelGGL((dirac_kernel<MODE, LCP>), dgrid, dblock, 0, s, a);    \
+    if (dgrid.x > 0) hipLaunchKernelGGL((dirac_kernel<MODE, DLCP>), dgrid, dblock, 0, s, a);   \
     if (grid.x == 0) break;                                                                    \
     if (a.direct) {                                                                            \
       if (first)                                                                               \
@@ -658,16 +672,20 @@ int launch_mode(const AnaArgs &a, int nthreads, bool first, size_t lds, void *st
         hipLaunchKernelGGL((kernel<false, MODE, LCP>), grid, block, lds, s, a);         \
     }                                                                                          \
     break;
+#define FHS_ANA_CASE(LCP) FHS_ANA_CASE2(LCP, LCP)
   switch (a.Lcp) {
     FHS_ANA_CASE(4)
     FHS_ANA_CASE(8)
+    FHS_ANA_CASE2(12, 16)
     FHS_ANA_CASE(16)
+    FHS_ANA_CASE2(20, 32)
     FHS_ANA_CASE(32)
     FHS_ANA_CASE(64)
     default:
-      return fail(FHS_EUNSUPPORTED, "analysis: lanes per sub-cube must be 4..64");
+      return fail(FHS_EUNSUPPORTED, "analysis: lanes per sub-cube must be 4, 8, 12, 16, 20, 32 or 64");
   }
 #undef FHS_ANA_CASE
+#undef FHS_ANA_CASE2
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return fail(FHS_EHIP, std::string("analysis launch: ") + hipGetErrorString(err));
   return FHS_OK;

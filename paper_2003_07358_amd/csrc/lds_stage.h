@@ -96,7 +96,42 @@ __device__ __forceinline__ float dpp_add(float v, int ctrl_tag) {
   return v + __int_as_float(o);
 }
 
+// Lane segments.  A power-of-two width lcp tiles the workgroup (thread t is
+// lane t % lcp of segment t / lcp).  The dense widths (12 and 20: a multiple of
+// 4 that is not a power of two) tile each wave with 64 / lcp whole segments,
+// the remaining 64 mod lcp lanes of the wave being idle: they alias lane 0 of
+// the wave's first segment (so every address they form is a valid one) and
+// must store nothing.
+__device__ __forceinline__ constexpr bool dense_width(int lcp) { return (lcp & (lcp - 1)) != 0; }
+
+__device__ __forceinline__ void seg_map(int tid, int lcp, int &lane, int &seg, bool &idle) {
+  if (!dense_width(lcp)) {
+    lane = tid % lcp;
+    seg = tid / lcp;
+    idle = false;
+  } else {
+    const int ln = tid & 63, g = 64 / lcp;
+    idle = ln >= g * lcp;
+    lane = idle ? 0 : ln % lcp;
+    seg = (tid >> 6) * g + (idle ? 0 : ln / lcp);
+  }
+}
+
+// Whole segments of a dense width per workgroup of `threads` threads.
+__host__ __device__ __forceinline__ int dense_segments(int threads, int lcp) { return (threads / 64) * (64 / lcp); }
+
 __device__ __forceinline__ float seg_sum(float v, int lcp) {
+  if (dense_width(lcp)) {
+    // quad sums (every lane of a quad gets the same bits), then the lcp / 4
+    // quad sums of the segment fetched and added in one fixed order
+    v = dpp_add(v, 0);
+    v = dpp_add(v, 1);
+    const int base = ((threadIdx.x & 63) / lcp) * lcp * 4;
+    const int iv = __float_as_int(v);
+    float s = __int_as_float(__builtin_amdgcn_ds_bpermute(base, iv));
+    for (int j = 1; j < lcp / 4; ++j) s += __int_as_float(__builtin_amdgcn_ds_bpermute(base + 16 * j, iv));
+    return s;
+  }
   if (lcp >= 2) v = dpp_add(v, 0);
   if (lcp >= 4) v = dpp_add(v, 1);
   if (lcp >= 8) v = dpp_add(v, 2);

@@ -87,8 +87,14 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   p->C = c.n_sub;
   p->Lc = c.nchan / c.n_sub;
   p->Q = c.qy * c.qx;
-  int lcp = 4;  // lanes per sub-cube: a power of two >= L_c, at least 4
+  // lanes per sub-cube: a power of two >= L_c, at least 4; L_c = 12 and 20
+  // run dense (5 and 3 segments per wave instead of 4 and 2 padded ones)
+  int lcp = 4;
   while (lcp < p->Lc) lcp *= 2;
+#ifndef FHS_DENSE_LANES
+#define FHS_DENSE_LANES 1
+#endif
+  if (FHS_DENSE_LANES && (p->Lc == 12 || p->Lc == 20)) lcp = p->Lc;
   p->Lcp = lcp;
   p->lc16 = (p->Lc + 15) / 16 * 16;
 
@@ -214,6 +220,7 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
     t.ana_phase = 4;
     t.syn_rows = 64;
     t.fin_rows = 128;
+    t.fin_waves = 8;
     // largest S (at most 64 / 32 / 16 by channel count) whose reconstruction
     // tile fits in 64 KB of LDS
     t.nuc_seg = 64;
@@ -336,6 +343,7 @@ int fhs_plan_set_tuning(fhs_plan *p, const fhs_tuning *t) {
     return fail(FHS_EINVAL, "nuc_chunk_rows below the workspace's minimum (" + std::to_string(p->nuc_chunk_min) + ")");
   if (t->concurrent != 0 && t->concurrent != 1) return fail(FHS_EINVAL, "concurrent must be 0 or 1");
   if (t->ana_direct != 0 && t->ana_direct != 1) return fail(FHS_EINVAL, "ana_direct must be 0 or 1");
+  if (t->fin_waves != 4 && t->fin_waves != 6 && t->fin_waves != 8) return fail(FHS_EINVAL, "fin_waves must be 4, 6 or 8");
   p->tune = *t;
   return FHS_OK;
 }

@@ -158,8 +158,13 @@ __device__ __forceinline__ void syn_basis(const SynArgs &A, const SynBand &B, in
   constexpr int H = NTAP / 2;
   const int L = A.L, Lcp = A.Lcp, C = A.C, Lc = A.Lc;
   const int tid = threadIdx.x;
-  const int lane = tid % Lcp, grp = tid / Lcp, c = grp % C, kq = grp / C;
-  const bool lv = lane < Lc;
+  int lane, grp;
+  bool idle;
+  seg_map(tid, Lcp, lane, grp, idle);
+  // (segments past the tile's tk columns, possible with dense widths, work
+  // on column 0 and store nothing)
+  const int c = grp % C, kq = grp / C < A.tk ? grp / C : 0;
+  const bool lv = !idle && lane < Lc && grp / C < A.tk;
   const int p = c * Lc + lane;
   const int strip = wg % B.strips, yb = wg / B.strips;
   const int kx0 = B.x_begin / 2 + strip * A.tk;
@@ -321,8 +326,11 @@ syn_final_kernel(SynFinalArgs A) {
   extern __shared__ float smem[];
   const int L = A.L, Lcp = A.Lcp, C = A.C, Lc = A.Lc;
   const int tid = threadIdx.x;
-  const int lane = tid % Lcp, grp = tid / Lcp, c = grp % C, kq = grp / C;
-  const bool lv = lane < Lc;
+  int lane, grp;
+  bool idle;
+  seg_map(tid, Lcp, lane, grp, idle);
+  const int c = grp % C, kq = grp / C < A.tk ? grp / C : 0;
+  const bool lv = !idle && lane < Lc && grp / C < A.tk;
   const int p = c * Lc + lane;
   const int ch = c + lane * C;
   const int strip = blockIdx.x % A.strips, yb = blockIdx.x / A.strips;

@@ -97,6 +97,11 @@ extern "C" int fhs_plan_autotune(fhs_plan *p, const float *xcheck, float *pdual,
     c.fin_rows = rows;
     trial(c);
   }
+  for (int waves : {4, 6, 8}) {
+    fhs_tuning c = best;
+    c.fin_waves = waves;
+    trial(c);
+  }
   for (int seg : {16, 32, 64}) {
     fhs_tuning c = best;
     c.nuc_seg = seg;

@@ -115,13 +115,13 @@ def test_compute_without_workspace_is_an_error():
 def test_tuning_roundtrip_and_validation():
     plan = fhs.Plan(256, 256, 20, 2, 2, 1, 32, 32, 4)
     t = plan.tuning
-    assert t["ana_rows"][:4] == [64, 64, 64, 64] and t["concurrent"] == 1
+    assert t["ana_rows"][:4] == [64, 64, 64, 64] and t["concurrent"] == 1 and t["fin_waves"] == 8
     assert t["nuc_seg"] in (16, 32, 64)
     plan.tuning = {"ana_rows": [32, 64, 128, 16, 64, 64], "fin_rows": 256, "nuc_seg": 16}
     t2 = plan.tuning
     assert t2["ana_rows"][:4] == [32, 64, 128, 16] and t2["fin_rows"] == 256 and t2["nuc_seg"] == 16
     for bad in ({"ana_rows": [12, 64, 64, 64, 64, 64]}, {"ana_phase": 3}, {"syn_rows": 20}, {"nuc_seg": 48},
-                {"nuc_chunk_rows": 0}, {"concurrent": 2}, {"ana_direct": 3}):
+                {"nuc_chunk_rows": 0}, {"concurrent": 2}, {"ana_direct": 3}, {"fin_waves": 5}):
         with pytest.raises(fhs.FhsError):
             plan.tuning = bad
     assert plan.tuning == t2   # a rejected setting leaves the plan unchanged

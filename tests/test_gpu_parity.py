@@ -29,6 +29,11 @@ CASES = {
     "lc5_odd_48x40x5_q1x1": dict(ny=48, nx=40, L=5, blobs=6),
     "tiny_7x9x3_levels2": dict(ny=7, nx=9, L=3, levels=2, blobs=2),
     "c4_64x64x12_q4x4_o0": dict(ny=64, nx=64, L=12, qy=4, qx=4, C=4, blobs=10),
+    # dense lane segments (L_c = 12 or 20): one sub-cube; two sub-cubes; seven
+    # sub-cubes, whose segments do not fill the waves evenly
+    "lc12_72x60x12_q2x2": dict(ny=72, nx=60, L=12, qy=2, qx=2, oy=8, ox=8, blobs=8),
+    "c2_lc20_60x52x40_q2x1": dict(ny=60, nx=52, L=40, qy=2, qx=1, C=2, oy=6, ox=0, blobs=8),
+    "c7_lc12_40x36x84": dict(ny=40, nx=36, L=84, C=7, blobs=6),
 }
 
 
