@@ -191,7 +191,7 @@ def main():
         # launch shapes picked on the workload itself (outside the timed region);
         # the duals it scribbles on are reset afterwards
         t0a = time.perf_counter()
-        tuning = plan.autotune(x_d, p_d, w_d, th_d, tb_d, mu_d, mub_d, g_d, reps=3)
+        tuning = plan.autotune(x_d, p_d, w_d, th_d, tb_d, mu_d, mub_d, g_d, reps=5)
         p_d.zero_()
         w_d.zero_()
         torch.cuda.synchronize()

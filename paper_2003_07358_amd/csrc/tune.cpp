@@ -71,52 +71,60 @@ extern "C" int fhs_plan_autotune(fhs_plan *p, const float *xcheck, float *pdual,
     }
     (void)fhs_plan_set_tuning(p, &best);
   };
-  for (int d : {0, 1}) {
-    fhs_tuning c = best;
-    c.ana_direct = d;
-    trial(c);
-  }
-  for (int j = 0; j < p->cfg.levels && j < kMaxLevels; ++j)
-    for (int rows : {8, 16, 32, 64, 128}) {
+  // two passes of coordinate descent (the fields interact: the second pass
+  // revisits each with the others settled); the second is skipped if the
+  // first changed nothing
+  for (int pass = 0; pass < 2; ++pass) {
+    const float pass_start = best_ms;
+    // the step's structure first (the two streams' balance), then the shapes
+    for (int conc : {0, 1}) {
       fhs_tuning c = best;
-      c.ana_rows[j] = rows;
+      c.concurrent = conc;
       trial(c);
     }
-  for (int ph : {1, 2, 4}) {
-    fhs_tuning c = best;
-    c.ana_phase = ph;
-    trial(c);
-  }
-  for (int rows : {32, 64, 128}) {
-    fhs_tuning c = best;
-    c.syn_rows = rows;
-    trial(c);
-  }
-  for (int rows : {64, 128, 256}) {
-    fhs_tuning c = best;
-    c.fin_rows = rows;
-    trial(c);
-  }
-  for (int waves : {4, 6, 8}) {
-    fhs_tuning c = best;
-    c.fin_waves = waves;
-    trial(c);
-  }
-  for (int seg : {16, 32, 64}) {
-    fhs_tuning c = best;
-    c.nuc_seg = seg;
-    trial(c);
-  }
-  const int ch0 = best.nuc_chunk_rows;
-  for (int f : {1, 2, 4}) {
-    fhs_tuning c = best;
-    c.nuc_chunk_rows = std::max(p->nuc_chunk_min, ch0 * f / 2);
-    trial(c);
-  }
-  for (int conc : {0, 1}) {
-    fhs_tuning c = best;
-    c.concurrent = conc;
-    trial(c);
+    const int ch0 = p->nuc_chunk_min * 2;  // (the default chunk)
+    for (int f : {1, 2, 4, 8, 16}) {
+      fhs_tuning c = best;
+      c.nuc_chunk_rows = std::max(p->nuc_chunk_min, ch0 * f / 2);
+      trial(c);
+    }
+    for (int seg : {16, 32, 64}) {
+      fhs_tuning c = best;
+      c.nuc_seg = seg;
+      trial(c);
+    }
+    for (int d : {0, 1}) {
+      fhs_tuning c = best;
+      c.ana_direct = d;
+      trial(c);
+    }
+    for (int j = 0; j < p->cfg.levels && j < kMaxLevels; ++j)
+      for (int rows : {8, 16, 32, 64, 128}) {
+        fhs_tuning c = best;
+        c.ana_rows[j] = rows;
+        trial(c);
+      }
+    for (int ph : {1, 2, 4}) {
+      fhs_tuning c = best;
+      c.ana_phase = ph;
+      trial(c);
+    }
+    for (int rows : {32, 64, 128}) {
+      fhs_tuning c = best;
+      c.syn_rows = rows;
+      trial(c);
+    }
+    for (int rows : {64, 128, 256}) {
+      fhs_tuning c = best;
+      c.fin_rows = rows;
+      trial(c);
+    }
+    for (int waves : {4, 6, 8}) {
+      fhs_tuning c = best;
+      c.fin_waves = waves;
+      trial(c);
+    }
+    if (best_ms == pass_start) break;
   }
   (void)fhs_plan_set_tuning(p, &best);
   (void)hipEventDestroy(e0);
