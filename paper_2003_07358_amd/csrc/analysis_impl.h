@@ -675,14 +675,17 @@ int launch_mode(const AnaArgs &a, int nthreads, bool first, size_t lds, void *st
 #define FHS_ANA_CASE(LCP) FHS_ANA_CASE2(LCP, LCP)
   switch (a.Lcp) {
     FHS_ANA_CASE(4)
+    FHS_ANA_CASE2(6, 8)
     FHS_ANA_CASE(8)
+    FHS_ANA_CASE2(10, 16)
     FHS_ANA_CASE2(12, 16)
     FHS_ANA_CASE(16)
+    FHS_ANA_CASE2(18, 32)
     FHS_ANA_CASE2(20, 32)
     FHS_ANA_CASE(32)
     FHS_ANA_CASE(64)
     default:
-      return fail(FHS_EUNSUPPORTED, "analysis: lanes per sub-cube must be 4, 8, 12, 16, 20, 32 or 64");
+      return fail(FHS_EUNSUPPORTED, "analysis: unsupported lanes per sub-cube");
   }
 #undef FHS_ANA_CASE
 #undef FHS_ANA_CASE2

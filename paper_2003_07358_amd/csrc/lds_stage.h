@@ -97,11 +97,11 @@ __device__ __forceinline__ float dpp_add(float v, int ctrl_tag) {
 }
 
 // Lane segments.  A power-of-two width lcp tiles the workgroup (thread t is
-// lane t % lcp of segment t / lcp).  The dense widths (12 and 20: a multiple of
-// 4 that is not a power of two) tile each wave with 64 / lcp whole segments,
-// the remaining 64 mod lcp lanes of the wave being idle: they alias lane 0 of
-// the wave's first segment (so every address they form is a valid one) and
-// must store nothing.
+// lane t % lcp of segment t / lcp).  The dense widths (6, 10, 12, 18, 20: even,
+// not a power of two) tile each wave with 64 / lcp whole segments, the
+// remaining 64 mod lcp lanes of the wave being idle: they alias lane 0 of the
+// wave's first segment (so every address they form is a valid one) and must
+// store nothing.
 __device__ __forceinline__ constexpr bool dense_width(int lcp) { return (lcp & (lcp - 1)) != 0; }
 
 __device__ __forceinline__ void seg_map(int tid, int lcp, int &lane, int &seg, bool &idle) {
@@ -122,14 +122,16 @@ __host__ __device__ __forceinline__ int dense_segments(int threads, int lcp) { r
 
 __device__ __forceinline__ float seg_sum(float v, int lcp) {
   if (dense_width(lcp)) {
-    // quad sums (every lane of a quad gets the same bits), then the lcp / 4
-    // quad sums of the segment fetched and added in one fixed order
+    // pair (or, for a multiple of 4, quad) sums, every lane of a pair / quad
+    // getting the same bits, then the segment's pair / quad sums fetched and
+    // added in one fixed order
+    const int grain = lcp % 4 == 0 ? 4 : 2;
     v = dpp_add(v, 0);
-    v = dpp_add(v, 1);
+    if (grain == 4) v = dpp_add(v, 1);
     const int base = ((threadIdx.x & 63) / lcp) * lcp * 4;
     const int iv = __float_as_int(v);
     float s = __int_as_float(__builtin_amdgcn_ds_bpermute(base, iv));
-    for (int j = 1; j < lcp / 4; ++j) s += __int_as_float(__builtin_amdgcn_ds_bpermute(base + 16 * j, iv));
+    for (int j = 1; j < lcp / grain; ++j) s += __int_as_float(__builtin_amdgcn_ds_bpermute(base + 4 * grain * j, iv));
     return s;
   }
   if (lcp >= 2) v = dpp_add(v, 0);

@@ -87,14 +87,15 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   p->C = c.n_sub;
   p->Lc = c.nchan / c.n_sub;
   p->Q = c.qy * c.qx;
-  // lanes per sub-cube: a power of two >= L_c, at least 4; L_c = 12 and 20
-  // run dense (5 and 3 segments per wave instead of 4 and 2 padded ones)
+  // lanes per sub-cube: a power of two >= L_c, at least 4; L_c = 6, 10, 12,
+  // 18 and 20 run dense (10, 6, 5, 3 and 3 segments per wave instead of 8, 4,
+  // 4, 2 and 2 padded ones)
   int lcp = 4;
   while (lcp < p->Lc) lcp *= 2;
 #ifndef FHS_DENSE_LANES
 #define FHS_DENSE_LANES 1
 #endif
-  if (FHS_DENSE_LANES && (p->Lc == 12 || p->Lc == 20)) lcp = p->Lc;
+  if (FHS_DENSE_LANES && (p->Lc == 6 || p->Lc == 10 || p->Lc == 12 || p->Lc == 18 || p->Lc == 20)) lcp = p->Lc;
   p->Lcp = lcp;
   p->lc16 = (p->Lc + 15) / 16 * 16;
 

@@ -34,6 +34,10 @@ CASES = {
     "lc12_72x60x12_q2x2": dict(ny=72, nx=60, L=12, qy=2, qx=2, oy=8, ox=8, blobs=8),
     "c2_lc20_60x52x40_q2x1": dict(ny=60, nx=52, L=40, qy=2, qx=1, C=2, oy=6, ox=0, blobs=8),
     "c7_lc12_40x36x84": dict(ny=40, nx=36, L=84, C=7, blobs=6),
+    # dense segments of even, non-multiple-of-4 widths (pair sums)
+    "lc6_50x44x6_q2x2": dict(ny=50, nx=44, L=6, qy=2, qx=2, oy=6, ox=6, blobs=8),
+    "c10_lc10_40x36x100_q2x2": dict(ny=40, nx=36, L=100, qy=2, qx=2, C=10, oy=4, ox=4, blobs=6),
+    "c4_lc18_36x30x72_q2x1": dict(ny=36, nx=30, L=72, qy=2, qx=1, C=4, oy=4, ox=0, blobs=6),
 }
 
 
