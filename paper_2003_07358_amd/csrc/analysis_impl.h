@@ -9,7 +9,8 @@
 // kernel tiles the global transform.
 //
 // Work decomposition: a workgroup owns TKX coefficient columns (all channel
-// positions of every sub-cube, LCP lanes per sub-cube) and a run of
+// positions of every sub-cube, a segment of LCP lanes per sub-cube: padded
+// to a power of two, or dense, see seg_map) and a run of
 // coefficient rows of one basis at one level.  It streams input rows top to
 // bottom: step g filters input rows 2g, 2g+1 (relative to the first needed row)
 // horizontally into a per-thread FP64 register ring, and once the ring holds
@@ -27,9 +28,10 @@
 // a fixed four per emitted row, so that the wait at a phase boundary can leave
 // the previous phase's stores in flight.
 //
-// Launch order is XCD-aware: workgroup id -> XCD id % 8; each XCD walks a
-// contiguous run of tiles and, for each tile, the 8 bases one after the other,
-// so the input segments of a tile are fetched from HBM once per XCD L2.
+// Launch order: basis-major (every tile of the first basis, then of the
+// second, ...).  Orders that place the 8 bases of a tile on one XCD (so that
+// its L2 serves the shared input rows) are kept behind FHS_ANA_XCD; they
+// measured no faster.
 //
 // Arithmetic: FP32 in / FP32 out, FP64 accumulation (detail coefficients are
 // differences of large neighbouring values), unnormalised filters with the

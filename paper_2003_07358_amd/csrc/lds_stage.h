@@ -77,11 +77,12 @@ __device__ __forceinline__ void wait_loads_and_sync() {
 
 __device__ __forceinline__ void drain_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Sum over the aligned segment of `lcp` lanes (a power of two dividing 64),
-// every lane of the segment receiving the sum.  Butterfly with cross-lane
-// moves that stay in the VALU where possible: DPP quad permutations (lane ^ 1,
-// lane ^ 2), DPP half-row and row mirrors (which pair the two halves of 8 and
-// of 16 lanes), a ds_swizzle xor 16 and, for 64 lanes, a bpermute.
+// Sum over the segment of `lcp` lanes holding this lane, every lane of the
+// segment receiving the sum (dense widths: see seg_sum).  Power-of-two widths
+// (aligned segments): a butterfly with cross-lane moves that stay in the VALU
+// where possible: DPP quad permutations (lane ^ 1, lane ^ 2), DPP half-row and
+// row mirrors (which pair the two halves of 8 and of 16 lanes), a ds_swizzle
+// xor 16 and, for 64 lanes, a bpermute.
 // (update_dpp with bound_ctrl lets the compiler fold the move into the add:
 // one v_add_f32 with a DPP source)
 __device__ __forceinline__ float dpp_add(float v, int ctrl_tag) {
