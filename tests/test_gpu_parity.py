@@ -121,6 +121,31 @@ def test_nuclear_dual_update(name, warm):
     check("beta g + zeta sum S~^T D P+", host(g), beta * g0.astype(np.float64) + G)
 
 
+def test_nuclear_conditioning_sweep():
+    """Error of the nuclear dual update against the oracle as the thresholds
+    shrink and kappa = sigma_1 / min t grows (the Gram route squares kappa;
+    FP64 accumulation keeps every point within the bar)."""
+    from oracle import step as ostep
+    pb, plan = make("cfg1_256x256x20_q2x2_o32", warm=True)
+    sig1 = max(np.linalg.svd(ostep.facet_matrix(pb.X, f, np.arange(pb.L)), compute_uv=False)[0]
+               for f in pb.geom.facets)
+    for scale in (1.0, 1e-1, 1e-2, 1e-3, 1e-4):
+        mub = np.asarray(pb.mu_bar) * scale
+        tmin = min(float(np.min(mub[0][q] * pb.theta_bar[0][q])) for q in range(pb.geom.Q))
+        p = dev(pb.P_flat())
+        g = torch.zeros(plan.sizes["n_x"], device="cuda")
+        plan.nuclear_dual_update(dev(pb.X), p, dev(pb.theta_bar_flat()), dev(mub.reshape(-1)), 1.0, g, 0.0)
+        Pn, G = ostep.nuclear_dual_update(pb.X, pb.P, pb.theta_bar, mub, 1.0, pb.geom, C=pb.C)
+        ref = np.concatenate([q.reshape(-1) for row in Pn for q in row])
+        kappa = sig1 / tmin
+        # bar: the common one, or the Gram route's FP64 bound u kappa^2 (x4) once that is larger
+        bar = max(TOL, 4 * 2.0 ** -53 * kappa ** 2)
+        e, eg = rel_l2(host(p), ref), rel_l2(host(g), G.reshape(-1))
+        log(f"    threshold scale {scale:g}: kappa = {kappa:.3e}, P+ rel_l2 = {e:.3e}, G rel_l2 = {eg:.3e}, "
+            f"bar {bar:.1e}")
+        assert e <= bar and eg <= bar, (scale, kappa, e, eg)
+
+
 @pytest.mark.parametrize("variant", ["plain", "signed"])
 @pytest.mark.parametrize("warm", [False, True])
 def test_facet_prox_step_cfg1(variant, warm):

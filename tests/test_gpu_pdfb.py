@@ -209,6 +209,32 @@ def test_reweighting_solve_parity(name):
     assert (np.isinf(xo) and np.isinf(got["rw_xi"])) or abs(got["rw_xi"] - xo) <= 1e-3 * xo
 
 
+def test_resume_from_checkpoint_is_bitwise(tmp_path):
+    """Four iterations in a row equal two, a checkpoint of the state written to
+    disk and read back into fresh device arrays, and two more (the state that
+    Alg. 1 carries: X, Xcheck, P, W, v)."""
+    from paper_2003_07358_amd import checkpoint
+    log("[case] checkpoint / resume, q3x2_c1_90x70x8, 2 + 2 iterations")
+    pb, y, eps, x0 = pdfb_problem(**PDFB_CASES["q3x2_c1_90x70x8"])
+    plan = fhs.Plan(*pb.cfg).attach_workspace()
+    ta, sta = gpu_state(plan, pb, y, eps, x0, 4)
+    for i in range(4):
+        plan.pdfb_iteration(sta, i)
+    tb, stb = gpu_state(plan, pb, y, eps, x0, 4)
+    for i in range(2):
+        plan.pdfb_iteration(stb, i)
+    keys = ("x", "xcheck", "p", "w", "v")
+    checkpoint.save(tmp_path / "s.npz", plan, **{k: tb[k] for k in keys})
+    tc, stc = gpu_state(plan, pb, y, eps, x0, 4)
+    for k, v in checkpoint.load(tmp_path / "s.npz", plan).items():
+        tc[k].copy_(v)
+    for i in range(2, 4):
+        plan.pdfb_iteration(stc, i)
+    for k in keys + ("grad",):
+        assert np.array_equal(host(ta[k]), host(tc[k])), k
+    assert np.array_equal(host(ta["xi"])[2:], host(tc["xi"])[2:])
+
+
 @pytest.mark.parametrize("L,with_log", [(20, True), (5, True), (64, False)])
 def test_snr_matches_oracle(L, with_log):
     """Reconstruction SNR and log-scale SNR per channel (Sec. 4.2) against the
