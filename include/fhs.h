@@ -144,7 +144,8 @@ typedef struct {
   int32_t nuc_seg;         /* pixels per staged segment of the nuclear kernels (16, 32, 64) */
   int32_t nuc_chunk_rows;  /* window rows per nuclear workgroup (>= the plan's minimum) */
   int32_t concurrent;      /* 1: the nuclear chain runs on a second stream beside the wavelet chain */
-  int32_t ana_direct;      /* 1: analysis loads taps, W and theta straight into registers (no LDS) */
+  int32_t ana_direct;      /* bit j set: the analysis of level j+1 loads taps, W and theta straight
+                              into registers (no LDS); bit mask over the levels */
   int32_t fin_waves;       /* wavefronts per level-1 synthesis workgroup (4, 6 or 8) */
 } fhs_tuning;
 

@@ -98,7 +98,7 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     a.Lcp = p->Lcp;
     a.tkx1 = tkx1;
     a.tky = p->tune.ana_rows[j];
-    a.direct = p->tune.ana_direct;
+    a.direct = (p->tune.ana_direct >> j) & 1;
     a.mode = mode;
     // staged row: [sub-cube][column][lane slot], columns of the widest filter
     // (plus one pad column per sub-cube block when there are several), in

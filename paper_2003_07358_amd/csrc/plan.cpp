@@ -343,7 +343,8 @@ int fhs_plan_set_tuning(fhs_plan *p, const fhs_tuning *t) {
   if (t->nuc_chunk_rows < p->nuc_chunk_min)
     return fail(FHS_EINVAL, "nuc_chunk_rows below the workspace's minimum (" + std::to_string(p->nuc_chunk_min) + ")");
   if (t->concurrent != 0 && t->concurrent != 1) return fail(FHS_EINVAL, "concurrent must be 0 or 1");
-  if (t->ana_direct != 0 && t->ana_direct != 1) return fail(FHS_EINVAL, "ana_direct must be 0 or 1");
+  if (t->ana_direct < 0 || t->ana_direct >= (1 << kMaxLevels))
+    return fail(FHS_EINVAL, "ana_direct must be a bit mask of levels (0 .. 63)");
   if (t->fin_waves != 4 && t->fin_waves != 6 && t->fin_waves != 8) return fail(FHS_EINVAL, "fin_waves must be 4, 6 or 8");
   p->tune = *t;
   return FHS_OK;

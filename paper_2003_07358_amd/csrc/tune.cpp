@@ -93,17 +93,18 @@ extern "C" int fhs_plan_autotune(fhs_plan *p, const float *xcheck, float *pdual,
       c.nuc_seg = seg;
       trial(c);
     }
-    for (int d : {0, 1}) {
-      fhs_tuning c = best;
-      c.ana_direct = d;
-      trial(c);
-    }
-    for (int j = 0; j < p->cfg.levels && j < kMaxLevels; ++j)
+    for (int j = 0; j < p->cfg.levels && j < kMaxLevels; ++j) {
+      for (int d : {0, 1}) {
+        fhs_tuning c = best;
+        c.ana_direct = (best.ana_direct & ~(1 << j)) | (d << j);
+        trial(c);
+      }
       for (int rows : {8, 16, 32, 64, 128}) {
         fhs_tuning c = best;
         c.ana_rows[j] = rows;
         trial(c);
       }
+    }
     for (int ph : {1, 2, 4}) {
       fhs_tuning c = best;
       c.ana_phase = ph;

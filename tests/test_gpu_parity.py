@@ -267,7 +267,7 @@ def test_direct_analysis_matches_staged(name):
     pb, plan = make(name, warm=True)
     x = dev(pb.X)
     outs = []
-    for direct in (0, 1):
+    for direct in (0, 63, 0b0101):     # staged, direct at every level, mixed
         plan.tuning = {"ana_direct": direct}
         w0 = torch.empty(plan.sizes["n_w"], dtype=torch.float32, device="cuda")
         plan.sara_analysis(x, w0)
@@ -277,7 +277,8 @@ def test_direct_analysis_matches_staged(name):
         tb = torch.empty(plan.sizes["n_theta_bar"], dtype=torch.float64, device="cuda")
         plan.reweight(x, dev(pb.mu), dev(pb.mu_bar_flat()), th, tb)
         outs.append([host(w0), host(w1), host(g1), host(th)])
-    for nm, a, b in zip(("Psi^dagger x", "W+", "G", "theta"), outs[1], outs[0]):
-        log(f"    {nm}: max |direct - staged| = {np.max(np.abs(a - b)):.3e}")
-        assert np.array_equal(a, b), nm
+    for o in outs[1:]:
+        for nm, a, b in zip(("Psi^dagger x", "W+", "G", "theta"), o, outs[0]):
+            log(f"    {nm}: max |direct - staged| = {np.max(np.abs(a - b)):.3e}")
+            assert np.array_equal(a, b), nm
     check("W+ (direct)", outs[1][1], np.concatenate(pb.oracle_l21()[0], axis=1).reshape(-1))
