@@ -71,9 +71,27 @@ def test_primal_update_properties():
     np.testing.assert_allclose(xn[free], (x - 0.33 * (g + v))[free], rtol=0, atol=1e-15)
     assert (xn[~free] == 0).all()
     np.testing.assert_allclose(xc + x, 2 * xn, atol=1e-15)
-    assert xi == pytest.approx(np.sqrt(np.sum((xn - x) ** 2) / np.sum(x ** 2)), rel=1e-13)
+    assert xi.shape == (1,)
+    assert xi[0] == pytest.approx(np.sqrt(np.sum((xn - x) ** 2) / np.sum(x ** 2)), rel=1e-13)
     _, _, xi0 = closure.primal_update(np.zeros_like(x), g, v, 0.33)
-    assert np.isinf(xi0)
+    assert np.isinf(xi0[0])
+
+
+def test_relative_variation_per_subcube():
+    """Alg. 2 measures the relative variation of each spectral sub-problem on
+    its own channels (channel-interleaved sub-cubes, Sec. 2.4.1): changing
+    only the channels of sub-cube 1 leaves xi_0 = 0, and a zero sub-cube gives
+    +inf whatever the others do."""
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0.5, 1.0, (5, 4, 6))
+    xn = x.copy()
+    xn[..., 1::3] *= 1.5
+    xi = closure.relative_variation(xn, x, C=3)
+    assert xi[0] == 0.0 and xi[2] == 0.0
+    assert xi[1] == pytest.approx(0.5, rel=1e-14)
+    x[..., 2::3] = 0.0
+    xi = closure.relative_variation(xn, x, C=3)
+    assert np.isinf(xi[2]) and xi[0] == 0.0
 
 
 def _objective(X, geom, mu, mu_bar, levels, L):
@@ -109,7 +127,7 @@ def test_pdfb_reaches_the_constrained_minimiser():
     v = np.zeros_like(y)
     for _ in range(500):
         x, xc, P, W, v, xi = closure.pdfb_iteration(x, xc, P, W, v, y, eps, theta, theta_bar, mu_v, mu_bar, geom)
-    assert xi < 1e-6
+    assert xi[0] < 1e-6
     assert (x >= 0).all()
     assert (np.linalg.norm(x - y, axis=(0, 1)) <= eps * (1 + 1e-5)).all()
     # Optimality (KKT) conditions of the convex problem, from the duals the
