@@ -239,16 +239,18 @@ int fhs_reweight(const fhs_plan *plan, const float *x, const double *upsilon,
  *   v      <- (I - proj_{B(y_l, eps_l)})(v + xcheck)   per channel l (Table 1)
  *   x+      = max(0, x - tau (grad + v))               (primal update, Table 1)
  *   xcheck <- 2 x+ - x,   x <- x+                      (extrapolation)
- *   *xi     = ||x+ - x||_F / ||x||_F  (+inf if x = 0)  (relative variation)
+ *   xi[c]   = ||x+_c - x_c||_F / ||x_c||_F             (relative variation of
+ *             spectral sub-cube c, channels c, c + C, ...; +inf if x_c = 0;
+ *             Alg. 2 solves each sub-problem on its own)
  * x, xcheck, v, y, grad: float32 [ny][nx][L] (natural channel order); eps:
- * float64 [L]; xi: one float64.  All device pointers; x, xcheck, v are
+ * float64 [L]; xi: float64 [C].  All device pointers; x, xcheck, v are
  * updated in place and must not alias y or grad.  The channel norms and xi
  * are accumulated in float64 in a fixed order (bitwise reproducible).  Uses
  * the plan's workspace. */
 int fhs_pdfb_closure(const fhs_plan *plan, float *x, float *xcheck, float *v, const float *y,
                      const double *eps, const float *grad, double tau, double *xi, void *stream);
 
-/* Reconstruction quality (Sec. 4.2), per channel l of the plan's cube:
+/* Reconstruction quality (Sec. 4.3), per channel l of the plan's cube:
  *   snr[l]     = 20 log10(||x_ref_l||_2 / ||x_ref_l - x_l||_2)
  *   snr_log[l] = the same on log10(z / eps_l + 1) of both images (term-wise)
  * in dB, +inf where the estimate equals the reference.  x_ref, x: float32
@@ -274,15 +276,15 @@ typedef struct {
   const double *mu;         /* [C]                                              */
   const double *mu_bar;     /* [C*Q]                                            */
   float *grad;              /* facet gradient, overwritten [ny][nx][L]          */
-  double *xi;               /* relative variation, one float64 per iteration    */
+  double *xi;               /* relative variations, C float64 per iteration     */
   double zeta, kappa, tau;  /* dual and primal step sizes (tau > 0)            */
 } fhs_pdfb_state;
 
 /* One iteration: fhs_facet_prox_step on xcheck (into grad), then
- * fhs_pdfb_closure, writing xi[iter]. */
+ * fhs_pdfb_closure, writing xi[iter * C .. iter * C + C - 1]. */
 int fhs_pdfb_iteration(const fhs_plan *plan, const fhs_pdfb_state *state, int32_t iter, void *stream);
 
-/* A HIP graph of n_iter consecutive iterations (xi[0 .. n_iter-1]), captured
+/* A HIP graph of n_iter consecutive iterations (xi[0 .. n_iter C - 1]), captured
  * on a stream of the library's own and instantiated; it bakes in the
  * pointers of *state and the plan's workspace, so those must outlive it and
  * launches that share them must not overlap.  Fails with FHS_EINVAL while
@@ -300,8 +302,8 @@ void fhs_graph_destroy(fhs_graph *graph);
  * PDFB run inside it (Alg. 2).  The paper's values: max_reweights 5,
  * min_iter 10, max_iter 2000, rw_tol = pdfb_tol = 1e-5, res_factor 1.01. */
 typedef struct {
-  int32_t max_reweights; /* T: at most this many PDFB runs                       */
-  double rw_tol;         /* the loop ends once ||X(t+1)-X(t)||/||X(t)|| <= rw_tol */
+  int32_t max_reweights; /* T: at most this many PDFB runs per sub-cube          */
+  double rw_tol;         /* a sub-cube's loop ends once its ||X_c(t+1)-X_c(t)||/||X_c(t)|| <= rw_tol */
   int32_t min_iter;      /* PDFB iterations always performed                    */
   int32_t max_iter;      /* PDFB iteration cap (>= 1 and >= min_iter)           */
   double pdfb_tol;       /* bound on the relative variation xi of the iterate   */
@@ -309,38 +311,44 @@ typedef struct {
 } fhs_solve_params;
 
 typedef struct {
-  int32_t runs;          /* PDFB runs performed (reweighting passes)            */
-  int64_t iterations;    /* PDFB iterations over all runs                       */
-  double rw_xi;          /* relative variation of the last run (+inf: X(t) = 0) */
-  double last_xi;        /* xi of the last iteration                            */
-  double last_res;       /* ||r|| tested after the last iteration               */
+  int32_t runs;          /* reweighting passes made (the most of any sub-cube)  */
+  int64_t iterations;    /* PDFB iterations over all sub-cubes and runs         */
 } fhs_solve_report;
 
 /* Algorithm 1 with the identity as measurement operator, every array
- * resident on the device:
- *   t = 0, xi = +inf
- *   while t < max_reweights and xi > rw_tol:
- *     theta, theta_bar <- weights from X (as fhs_reweight, with upsilon [C]
- *                         and upsilon_bar [C*Q], float64 device arrays)
- *     X(t) <- X (kept in x_prev), Xcheck <- X
- *     PDFB run (fhs_pdfb_iteration, iteration p writing state->xi[p]) while
- *       p < min_iter, or p < max_iter and (xi_p > pdfb_tol or
- *       ||r|| > res_factor ||eps||), where ||r||^2 = sum_l ||y_l - x_l||^2 for
- *       the iterate entering the last iteration (Alg. 2, residual step)
- *     xi <- ||X - X(t)||_F / ||X(t)||_F,  t <- t + 1
- * P, W and v are warm-started from one run to the next (they are never
- * reset).  All spectral sub-cubes advance together; the stopping quantities
- * are taken over the whole cube.  state->theta and state->theta_bar are
- * overwritten (they must be writable device memory), state->xi must hold
- * max_iter float64, x_prev is a float32 device array of the cube's size.
+ * resident on the device.  The spectral sub-cubes are independent
+ * sub-problems (Sec. 2.4.1): Alg. 1 loops "for c = 1 to C" around its
+ * reweighting loop and Alg. 2 solves one sub-problem, so every sub-cube c has
+ * its own pass counter, relative variations and stopping decisions:
+ *   t_c = 0, xi_c = +inf
+ *   while t_c < max_reweights and xi_c > rw_tol:
+ *     theta_c, theta_bar_c <- weights from X_c (as fhs_reweight, with
+ *                     upsilon [C] and upsilon_bar [C*Q], float64 device arrays)
+ *     X_c(t) <- X_c (kept in x_prev), Xcheck_c <- X_c
+ *     PDFB run on sub-cube c while p_c < min_iter, or p_c < max_iter and
+ *       (xi_{c,p} > pdfb_tol or ||r_c|| > res_factor ||eps_c||), where
+ *       ||r_c||^2 = sum_{l in c} ||y_l - x_l||^2 for the iterate entering the
+ *       last iteration (Alg. 2, residual step) and ||eps_c||^2 = sum_{l in c}
+ *       eps_l^2
+ *     xi_c <- ||X_c - X_c(t)||_F / ||X_c(t)||_F,  t_c <- t_c + 1
+ * The sub-cubes still running advance together (one launch per operator
+ * covers all of them); a sub-cube that has stopped keeps X, P, W, v, theta
+ * and theta_bar bit for bit while the others go on (the kernels read
+ * per-sub-cube flags kept in the workspace).  P, W and v are warm-started
+ * from one run to the next (they are never reset).  state->theta and
+ * state->theta_bar are overwritten (they must be writable device memory),
+ * state->xi must hold max_iter * C float64 (iteration p of the current pass
+ * writes xi[p C + c]), x_prev is a float32 device array of the cube's size.
  * The loop decides on the host: every iteration ends with a small
  * device-to-host copy (xi and the per-channel residual sums) and a
- * synchronization of `stream`.  iters (host, max_reweights int32, or NULL)
- * receives the iteration count of each run; report (host, or NULL) the
+ * synchronization of `stream`.  Host outputs (each NULL to skip):
+ * iters [max_reweights * C] int32, iters[t C + c] = iterations of pass t of
+ * sub-cube c (0 if it made no such pass); rw_xi [max_reweights * C] float64,
+ * the relative variation that ended each pass (+inf where none); report, the
  * summary.  Uses the plan's workspace. */
 int fhs_reweighting_solve(const fhs_plan *plan, const fhs_pdfb_state *state, const double *upsilon,
                           const double *upsilon_bar, float *x_prev, const fhs_solve_params *params,
-                          int32_t *iters, fhs_solve_report *report, void *stream);
+                          int32_t *iters, double *rw_xi, fhs_solve_report *report, void *stream);
 
 /* ---------------------------------------------------------------- diagnostics */
 

@@ -47,8 +47,7 @@ class _SolveParams(ctypes.Structure):
 
 
 class _SolveReport(ctypes.Structure):
-    _fields_ = [("runs", ctypes.c_int32), ("iterations", ctypes.c_int64), ("rw_xi", ctypes.c_double),
-                ("last_xi", ctypes.c_double), ("last_res", ctypes.c_double)]
+    _fields_ = [("runs", ctypes.c_int32), ("iterations", ctypes.c_int64)]
 
 
 SYMBOLS = {
@@ -94,8 +93,8 @@ SYMBOLS = {
                                           ctypes.c_void_p]),
     "fhs_reweighting_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_PdfbState), ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_SolveParams),
-                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_SolveReport),
-                                             ctypes.c_void_p]),
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(_SolveReport), ctypes.c_void_p]),
     "fhs_pdfb_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_PdfbState), ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_void_p)]),
     "fhs_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -320,7 +319,8 @@ class Plan:
     # ------------------------------------------------------------ PDFB iterations
     def pdfb_closure(self, x, xcheck, v, y, eps, grad, tau, xi):
         """Data-fidelity dual (identity operator), primal update, extrapolation;
-        xi: a one-element float64 device tensor receiving the relative variation."""
+        xi: a float64 device tensor of C elements receiving the relative
+        variation of each sub-cube."""
         import torch
         self._need_ws()
         n = self.sizes["n_x"]
@@ -328,7 +328,7 @@ class Plan:
             self._p, self._t(x, n, torch.float32, "x"), self._t(xcheck, n, torch.float32, "xcheck"),
             self._t(v, n, torch.float32, "v"), self._t(y, n, torch.float32, "y"),
             self._t(eps, self.L, torch.float64, "eps"), self._t(grad, n, torch.float32, "grad"), float(tau),
-            self._t(xi, 1, torch.float64, "xi"), _stream(x)))
+            self._t(xi, self.C, torch.float64, "xi"), _stream(x)))
 
     def snr(self, x_ref, x, eps=None):
         """Per-channel reconstruction SNR in dB (float64 device tensor [L]) and,
@@ -346,13 +346,16 @@ class Plan:
 
     def pdfb_state(self, x, xcheck, p, w, v, y, eps, theta, theta_bar, mu, mu_bar, grad, xi, zeta=1.0,
                    kappa=1.0, tau=0.33):
-        """Checked state block for pdfb_iteration / pdfb_graph (xi: float64, one
-        entry per iteration).  The tensors must stay alive while it is used."""
+        """Checked state block for pdfb_iteration / pdfb_graph (xi: float64, C
+        entries per iteration).  The state holds references to the tensors, so
+        they live at least as long as it (and any graph captured from it)."""
         import torch
         s = self.sizes
         n = s["n_x"]
         if not (isinstance(xi, torch.Tensor) and xi.is_cuda and xi.dtype == torch.float64 and xi.is_contiguous()):
             raise FhsError("xi: expected a contiguous float64 device tensor")
+        if xi.numel() < self.C or xi.numel() % self.C:
+            raise FhsError("xi: expected a multiple of C entries (C per iteration)")
         st = _PdfbState(
             self._t(x, n, torch.float32, "x"), self._t(xcheck, n, torch.float32, "xcheck"),
             self._t(p, s["n_p"], torch.float32, "p"), self._t(w, s["n_w"], torch.float32, "w"),
@@ -362,8 +365,9 @@ class Plan:
             self._t(mu, self.C, torch.float64, "mu"), self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"),
             self._t(grad, n, torch.float32, "grad"), ctypes.c_void_p(xi.data_ptr()),
             float(zeta), float(kappa), float(tau))
-        st.n_xi = xi.numel()
+        st.n_xi = xi.numel() // self.C
         st.device = x.device
+        st.keep = (x, xcheck, p, w, v, y, eps, theta, theta_bar, mu, mu_bar, grad, xi)
         return st
 
     def pdfb_iteration(self, state, it=0):
@@ -377,8 +381,10 @@ class Plan:
     def reweighting_solve(self, state, upsilon, upsilon_bar, x_prev, max_reweights=5, rw_tol=1e-5, min_iter=10,
                           max_iter=2000, pdfb_tol=1e-5, res_factor=1.01):
         """Alg. 1 (fhs_reweighting_solve) on a pdfb_state whose theta and
-        theta_bar tensors it overwrites; xi must hold max_iter entries.
-        Returns dict(runs, iterations, iters (per run), rw_xi, last_xi, last_res)."""
+        theta_bar tensors it overwrites; xi must hold max_iter * C entries.
+        Every sub-cube runs its own loops.  Returns dict(runs, iterations,
+        iters, rw_xi) with iters[c] (rw_xi[c]) the iteration counts (ending
+        relative variations) of sub-cube c's passes."""
         import torch
         self._need_ws()
         if max_iter > state.n_xi:
@@ -386,15 +392,18 @@ class Plan:
         s = self.sizes
         prm = _SolveParams(int(max_reweights), float(rw_tol), int(min_iter), int(max_iter), float(pdfb_tol),
                            float(res_factor))
-        iters = (ctypes.c_int32 * max(1, int(max_reweights)))()
+        T, C = int(max_reweights), self.C
+        iters = (ctypes.c_int32 * max(1, T * C))()
+        rw = (ctypes.c_double * max(1, T * C))()
         rep = _SolveReport()
         _check(self._lib.fhs_reweighting_solve(
             self._p, ctypes.byref(state), self._t(upsilon, self.C, torch.float64, "upsilon"),
             self._t(upsilon_bar, s["n_facets"], torch.float64, "upsilon_bar"),
-            self._t(x_prev, s["n_x"], torch.float32, "x_prev"), ctypes.byref(prm), iters, ctypes.byref(rep),
+            self._t(x_prev, s["n_x"], torch.float32, "x_prev"), ctypes.byref(prm), iters, rw, ctypes.byref(rep),
             ctypes.c_void_p(torch.cuda.current_stream(state.device).cuda_stream)))
-        return dict(runs=rep.runs, iterations=rep.iterations, iters=list(iters)[:rep.runs], rw_xi=rep.rw_xi,
-                    last_xi=rep.last_xi, last_res=rep.last_res)
+        per = [[iters[t * C + c] for t in range(T) if iters[t * C + c] > 0] for c in range(C)]
+        xis = [[rw[t * C + c] for t in range(len(per[c]))] for c in range(C)]
+        return dict(runs=rep.runs, iterations=rep.iterations, iters=per, rw_xi=xis)
 
     def pdfb_graph(self, state, n_iter):
         """HIP graph of n_iter iterations (xi[0 .. n_iter-1])."""

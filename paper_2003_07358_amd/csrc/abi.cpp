@@ -76,7 +76,8 @@ int ana_lds_buf(const AnaArgs &a, int P) {
 }
 
 int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, const double *mu, double inv_kappa,
-                 int mode, void *stream, int fy = -1, int fx = -1, int level = -1, bool with_dirac = true) {
+                 int mode, void *stream, int fy = -1, int fx = -1, int level = -1, bool with_dirac = true,
+                 const int32_t *active = nullptr) {
   int tkx1, nth;
   if (int rc = thread_cfg(p, &tkx1, &nth, kAnaThreads)) return rc;
   const int TKX = tkx1;
@@ -100,6 +101,7 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     a.tky = p->tune.ana_rows[j];
     a.direct = (p->tune.ana_direct >> j) & 1;
     a.mode = mode;
+    a.active = active;
     // staged row: [sub-cube][column][lane slot], columns of the widest filter
     // (plus one pad column per sub-cube block when there are several), in
     // whole copy chunks (256 words with 16-byte copies, else 64)
@@ -191,7 +193,7 @@ int syn_strips(int b, int e, int tk) { return e > b ? ceil_div((e - 1) / 2 - b /
 // update (left out of the analysis) with input xin, weights theta, mu, 1/kappa.
 int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, float beta, void *stream, int fy = -1,
                   int fx = -1, int level = -1, const float *xin = nullptr, const float *theta = nullptr,
-                  const double *mu = nullptr, double inv_kappa = 0.0) {
+                  const double *mu = nullptr, double inv_kappa = 0.0, const int32_t *active = nullptr) {
   int tk, nth;
   if (int rc = thread_cfg(p, &tk, &nth, FHS_SYN_THREADS)) return rc;
   const int L = p->L, levels = p->cfg.levels;
@@ -257,6 +259,7 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
   f.dirac = const_cast<float *>(w) + dirac_off(p) * L;
   f.x = x;
   f.xin = xin;
+  f.active = active;
   f.theta = theta;
   f.mu = mu;
   f.inv_kappa = inv_kappa;
@@ -324,7 +327,7 @@ int run_gather(const fhs_plan *p, const float *pdual, float *grad, double zeta, 
 // per-facet execution form.
 int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *theta_bar, const double *mu_bar,
                 double zeta, double *theta_bar_out, float *grad, float beta, int mode, void *stream,
-                bool no_gather = false, int q = -1) {
+                bool no_gather = false, int q = -1, const int32_t *active = nullptr) {
   NucArgs a;
   std::memset(&a, 0, sizeof(a));
   fill_geom(p, a.g);
@@ -344,6 +347,7 @@ int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *t
   a.mode = mode;
   a.q0 = q >= 0 ? q : 0;
   a.eig_q = q;
+  a.active = active;
   const int nspatial = q >= 0 ? 1 : p->Q;
   const int nf = q >= 0 ? p->C : static_cast<int>(p->facets.size());
   int rc;
@@ -384,7 +388,53 @@ int run_gather(const fhs_plan *p, const float *pdual, float *grad, double zeta, 
   return rc;
 }
 
+int l21_update(const fhs_plan *p, const float *xcheck, float *w, const float *theta, const double *mu, double kappa,
+               float *grad, float beta, void *stream, const int32_t *active) {
+  // (the Dirac band's dual update runs inside the level-1 synthesis, which
+  // reads the updated coefficient right away)
+  if (int rc = run_analysis(p, xcheck, w, const_cast<float *>(theta), mu, 1.0 / kappa, 1, stream, -1, -1, -1, false,
+                            active))
+    return rc;
+  return run_synthesis(p, w, grad, static_cast<float>(kappa), beta, stream, -1, -1, -1, xcheck, theta, mu, 1.0 / kappa,
+                       active);
+}
+
 }  // namespace
+
+namespace fhs {
+
+int facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, float *w, const float *theta,
+                    const double *theta_bar, const double *mu, const double *mu_bar, double zeta, double kappa,
+                    float *grad, void *stream, const int32_t *active) {
+  if (!p->side || !p->tune.concurrent) {
+    if (int rc = l21_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream, active)) return rc;
+    return run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, stream, false, -1, active);
+  }
+  // The two dual updates are independent until the gather: the nuclear
+  // chain (Gram, eigendecomposition, reconstruction) runs on the plan's side
+  // stream beside the wavelet chain, and the gather waits for both.
+  hipStream_t s0 = static_cast<hipStream_t>(stream), s1 = static_cast<hipStream_t>(p->side);
+  hipEvent_t fork = static_cast<hipEvent_t>(p->ev_fork), join = static_cast<hipEvent_t>(p->ev_join);
+  if (hipEventRecord(fork, s0) != hipSuccess || hipStreamWaitEvent(s1, fork, 0) != hipSuccess)
+    return fail(FHS_EHIP, "fork to the side stream failed");
+  int rc = run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, s1, true, -1, active);
+  const bool joined = hipEventRecord(join, s1) == hipSuccess;
+  if (rc == FHS_OK) rc = l21_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream, active);
+  if (!joined || hipStreamWaitEvent(s0, join, 0) != hipSuccess)
+    return rc ? rc : fail(FHS_EHIP, "join of the side stream failed");
+  if (rc) return rc;
+  return run_gather(p, pdual, grad, zeta, 1.0f, stream);
+}
+
+int reweight(const fhs_plan *p, const float *x, const double *upsilon, const double *upsilon_bar, float *theta,
+             double *theta_bar, void *stream, const int32_t *active) {
+  if (int rc = run_nuclear(p, x, nullptr, nullptr, upsilon_bar, 1.0, theta_bar, nullptr, 0.0f, 1, stream, false, -1,
+                           active))
+    return rc;
+  return run_analysis(p, x, nullptr, theta, upsilon, 1.0, 2, stream, -1, -1, -1, true, active);
+}
+
+}  // namespace fhs
 
 extern "C" {
 
@@ -405,11 +455,7 @@ int fhs_l21_dual_update(const fhs_plan *p, const float *xcheck, float *w, const 
   if (int rc = check_plan(p)) return rc;
   if (!xcheck || !w || !theta || !mu || !grad) return fail(FHS_EINVAL, "fhs_l21_dual_update: null array");
   if (!(kappa > 0)) return fail(FHS_EINVAL, "kappa must be positive");
-  // (the Dirac band's dual update runs inside the level-1 synthesis, which
-  // reads the updated coefficient right away)
-  if (int rc = run_analysis(p, xcheck, w, const_cast<float *>(theta), mu, 1.0 / kappa, 1, stream, -1, -1, -1, false))
-    return rc;
-  return run_synthesis(p, w, grad, static_cast<float>(kappa), beta, stream, -1, -1, -1, xcheck, theta, mu, 1.0 / kappa);
+  return l21_update(p, xcheck, w, theta, mu, kappa, grad, beta, stream, nullptr);
 }
 
 int fhs_nuclear_dual_update(const fhs_plan *p, const float *xcheck, float *pdual, const double *theta_bar,
@@ -427,24 +473,7 @@ int fhs_facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, fl
   if (!xcheck || !pdual || !w || !theta || !theta_bar || !mu || !mu_bar || !grad)
     return fail(FHS_EINVAL, "fhs_facet_prox_step: null array");
   if (!(zeta > 0) || !(kappa > 0)) return fail(FHS_EINVAL, "zeta and kappa must be positive");
-  if (!p->side || !p->tune.concurrent) {
-    if (int rc = fhs_l21_dual_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream)) return rc;
-    return run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, stream);
-  }
-  // The two dual updates are independent until the gather: the nuclear
-  // chain (Gram, eigendecomposition, reconstruction) runs on the plan's side
-  // stream beside the wavelet chain, and the gather waits for both.
-  hipStream_t s0 = static_cast<hipStream_t>(stream), s1 = static_cast<hipStream_t>(p->side);
-  hipEvent_t fork = static_cast<hipEvent_t>(p->ev_fork), join = static_cast<hipEvent_t>(p->ev_join);
-  if (hipEventRecord(fork, s0) != hipSuccess || hipStreamWaitEvent(s1, fork, 0) != hipSuccess)
-    return fail(FHS_EHIP, "fork to the side stream failed");
-  int rc = run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, s1, true);
-  const bool joined = hipEventRecord(join, s1) == hipSuccess;
-  if (rc == FHS_OK) rc = fhs_l21_dual_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream);
-  if (!joined || hipStreamWaitEvent(s0, join, 0) != hipSuccess)
-    return rc ? rc : fail(FHS_EHIP, "join of the side stream failed");
-  if (rc) return rc;
-  return run_gather(p, pdual, grad, zeta, 1.0f, stream);
+  return facet_prox_step(p, xcheck, pdual, w, theta, theta_bar, mu, mu_bar, zeta, kappa, grad, stream, nullptr);
 }
 
 int fhs_facet_prox_step_plain(const fhs_plan *p, const float *xcheck, float *pdual, float *w, const float *theta,
@@ -482,8 +511,7 @@ int fhs_reweight(const fhs_plan *p, const float *x, const double *upsilon, const
                  double *theta_bar, void *stream) {
   if (int rc = check_plan(p)) return rc;
   if (!x || !upsilon || !upsilon_bar || !theta || !theta_bar) return fail(FHS_EINVAL, "fhs_reweight: null array");
-  if (int rc = run_nuclear(p, x, nullptr, nullptr, upsilon_bar, 1.0, theta_bar, nullptr, 0.0f, 1, stream)) return rc;
-  return run_analysis(p, x, nullptr, theta, upsilon, 1.0, 2, stream);
+  return reweight(p, x, upsilon, upsilon_bar, theta, theta_bar, stream, nullptr);
 }
 
 }  // extern "C"

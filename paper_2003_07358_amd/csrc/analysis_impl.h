@@ -212,6 +212,8 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
   float thr = 0.0f;
   if (MODE == 1) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
   if (MODE == 2) thr = static_cast<float>(A.mu[c]);
+  // a frozen sub-cube keeps its old W (mode 1) or theta (mode 2)
+  const bool act = A.active == nullptr || A.active[c] != 0;
   const int wv = wave_id(), nwv = full_wave_count(), ln = tid & 63;
 
   // byte addresses of the tile's first column in coefficient row 0 of each
@@ -358,10 +360,11 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
         } else if (MODE == 1) {
           const float wold = wsg[sb * kAnaLaneSeg], th = tsg[sb * kAnaThSeg];
           const float u = lane < Lc ? wold + vb[sb] : 0.0f;
-          st_f32(shrink<LCP>(u, thr * th), rsrc(wbase[sb] + rb, run_bytes), vo, 0);
+          const float wn = shrink<LCP>(u, thr * th);
+          st_f32(act ? wn : wold, rsrc(wbase[sb] + rb, run_bytes), vo, 0);
         } else {
           const float r2 = seg_sum(vb[sb] * vb[sb], LCP);
-          st_f32(thr / (sqrtf(r2) + thr), rsrc(A.theta, static_cast<uint32_t>(A.theta_bytes)), vth0,
+          st_f32(thr / (sqrtf(r2) + thr), rsrc(A.theta, static_cast<uint32_t>(A.theta_bytes)), act ? vth0 : kOob,
                  tbase[sb] + ky * B.Kx * 4);
         }
       }
@@ -434,6 +437,7 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
   float thr = 0.0f;
   if (MODE == 1) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
   if (MODE == 2) thr = static_cast<float>(A.mu[c]);
+  const bool act = A.active == nullptr || A.active[c] != 0;  // frozen sub-cubes keep W / theta
   // byte offset of tap NTAP-1 (column 2 kx + 2 - NTAP) of this lane in a row;
   // tap m adds (NTAP-1-m) L 4 (negative columns wrap to huge offsets: zeros,
   // as do columns past the row)
@@ -505,11 +509,11 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
         } else if (MODE == 1) {
           // (lanes past Lc load channel 0: kept out of the norm)
           const float wn = shrink<LCP>(lv ? w[sb] + vb[sb] : 0.0f, thr * th[sb]);
-          if (ok) A.w[rowi * L + p] = wn;
+          if (ok && act) A.w[rowi * L + p] = wn;
         } else {
           const float vv = lv ? vb[sb] : 0.0f;
           const float r2 = seg_sum(vv * vv, LCP);
-          if (ok && lane == 0) A.theta[static_cast<int64_t>(c) * A.I + rowi] = thr / (sqrtf(r2) + thr);
+          if (ok && act && lane == 0) A.theta[static_cast<int64_t>(c) * A.I + rowi] = thr / (sqrtf(r2) + thr);
         }
       }
       if (!last && ok) B.ll_out[(static_cast<int64_t>(ky) * B.Kx + kx) * L + p] = static_cast<float>(ll);
@@ -557,6 +561,7 @@ __global__ void __launch_bounds__(kDiracThreads) dirac_kernel(AnaArgs A) {
   float thr = 0.0f;
   if (MODE == 1) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
   if (MODE == 2) thr = static_cast<float>(A.mu[c]);
+  const bool act = A.active == nullptr || A.active[c] != 0;  // frozen sub-cubes keep W / theta
   auto pixel = [&](int64_t li) { return full ? pix_first + li : pix_first + (li / rw) * B.in_nx + li % rw; };
   auto load = [&](int64_t l0, float (&v)[E], float (&w)[E], float (&th)[E]) __attribute__((always_inline)) {
 #pragma unroll
@@ -586,10 +591,10 @@ __global__ void __launch_bounds__(kDiracThreads) dirac_kernel(AnaArgs A) {
         if (ok) A.w[i * L + p] = x3;
       } else if (MODE == 1) {
         const float nw = l21_row_update(w[e], v[e], thr * th[e], LCP);
-        if (ok) A.w[i * L + p] = nw;
+        if (ok && act) A.w[i * L + p] = nw;
       } else {
         const float r2 = seg_sum(x3 * x3, LCP);
-        if (ok && lane == 0) A.theta[static_cast<int64_t>(c) * A.I + i] = thr / (sqrtf(r2) + thr);
+        if (ok && act && lane == 0) A.theta[static_cast<int64_t>(c) * A.I + i] = thr / (sqrtf(r2) + thr);
       }
     }
 #pragma unroll

@@ -11,9 +11,14 @@
 //   closure_factor : f_l = max(0, 1 - eps_l / ||d_l||)  (0 if ||d_l|| = 0),
 //                    so that (I - proj_B(y_l, eps_l))(v + xcheck) = f_l d
 //   closure_primal : v <- f_l d;  x+ = max(0, x - tau (grad + v));
-//                    xcheck <- 2 x+ - x;  x <- x+; block sums of
-//                    (x+ - x)^2 and x^2                           (FP64)
-//   closure_xi     : xi = ||x+ - x||_F / ||x||_F (+inf if x = 0)
+//                    xcheck <- 2 x+ - x;  x <- x+; per block and channel
+//                    the sums of (x+ - x)^2 and x^2               (FP64)
+//   closure_xi     : per spectral sub-cube c (channels c, c + C, ...; Alg. 2
+//                    solves each sub-problem on its own)
+//                    xi_c = ||x+_c - x_c||_F / ||x_c||_F (+inf if x_c = 0)
+//
+// With activity flags, the channels of a frozen sub-cube are read but not
+// written (its sums still come out, and are ignored by the caller).
 //
 // Thread layout: a block of 256 threads holds G = floor(256 / L) pixel groups
 // of L threads; thread (g, l) always works on channel l, so the channel sums
@@ -85,6 +90,8 @@ __global__ void __launch_bounds__(kThreads) closure_primal(ClosureArgs a) {
   double dx2 = 0.0, x2 = 0.0;
   if (t < G * L) {
     const int g = t / L, l = t - (t / L) * L;
+    // channel l belongs to sub-cube l mod C; a frozen sub-cube keeps x, xcheck, v
+    const bool act = a.active == nullptr || a.active[l % a.C] != 0;
     const double f = a.factor[l];
     const double tau = a.tau;
     for (int64_t p = p0 + g; p < p1; p += G) {
@@ -93,9 +100,11 @@ __global__ void __launch_bounds__(kThreads) closure_primal(ClosureArgs a) {
       const double d = static_cast<double>(a.v[e]) + static_cast<double>(a.xcheck[e]) - static_cast<double>(a.y[e]);
       const double vn = f * d;
       const double xn = fmax(0.0, xo - tau * (static_cast<double>(a.grad[e]) + vn));
-      a.v[e] = static_cast<float>(vn);
-      a.x[e] = static_cast<float>(xn);
-      a.xcheck[e] = static_cast<float>(2.0 * xn - xo);
+      if (act) {
+        a.v[e] = static_cast<float>(vn);
+        a.x[e] = static_cast<float>(xn);
+        a.xcheck[e] = static_cast<float>(2.0 * xn - xo);
+      }
       dx2 += (xn - xo) * (xn - xo);
       x2 += xo * xo;
     }
@@ -103,35 +112,44 @@ __global__ void __launch_bounds__(kThreads) closure_primal(ClosureArgs a) {
   sh0[t] = dx2;
   sh1[t] = x2;
   __syncthreads();
-  if (t == 0) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int i = 0; i < kThreads; ++i) {
-      s0 += sh0[i];
-      s1 += sh1[i];
-    }
-    a.part[2 * static_cast<int64_t>(blockIdx.x)] = s0;
-    a.part[2 * static_cast<int64_t>(blockIdx.x) + 1] = s1;
+  // per channel: the block's sums of (x+ - x)^2 and x^2, groups in order
+  if (t < L) {
+    a.part[static_cast<int64_t>(blockIdx.x) * 2 * L + t] = group_sum(sh0, G, L, t);
+    a.part[static_cast<int64_t>(blockIdx.x) * 2 * L + L + t] = group_sum(sh1, G, L, t);
   }
 }
 
+// One block: per channel, the block partials (split over the G groups, then
+// the groups in order); per sub-cube c, its channels c, c + C, ... in order;
+// xi_c = sqrt(sum (x+ - x)^2 / sum x^2) (+inf if x_c = 0).
 __global__ void __launch_bounds__(kThreads) closure_xi(ClosureArgs a) {
   __shared__ double sh0[kThreads], sh1[kThreads];
+  __shared__ double ch0[kThreads], ch1[kThreads];
   const int t = threadIdx.x;
+  const int L = a.L, G = kThreads / L;
   double s0 = 0.0, s1 = 0.0;
-  for (int b = t; b < a.nblocks; b += kThreads) {
-    s0 += a.part[2 * static_cast<int64_t>(b)];
-    s1 += a.part[2 * static_cast<int64_t>(b) + 1];
+  if (t < G * L) {
+    const int g = t / L, l = t - (t / L) * L;
+    for (int b = g; b < a.nblocks; b += G) {
+      s0 += a.part[static_cast<int64_t>(b) * 2 * L + l];
+      s1 += a.part[static_cast<int64_t>(b) * 2 * L + L + l];
+    }
   }
   sh0[t] = s0;
   sh1[t] = s1;
   __syncthreads();
-  if (t == 0) {
+  if (t < L) {
+    ch0[t] = group_sum(sh0, G, L, t);
+    ch1[t] = group_sum(sh1, G, L, t);
+  }
+  __syncthreads();
+  if (t < a.C) {
     double a0 = 0.0, a1 = 0.0;
-    for (int i = 0; i < kThreads; ++i) {
-      a0 += sh0[i];
-      a1 += sh1[i];
+    for (int l = t; l < L; l += a.C) {
+      a0 += ch0[l];
+      a1 += ch1[l];
     }
-    a.xi[0] = a1 > 0.0 ? sqrt(a0 / a1) : __builtin_huge_val();
+    a.xi[t] = a1 > 0.0 ? sqrt(a0 / a1) : __builtin_huge_val();
   }
 }
 

@@ -71,6 +71,7 @@ struct AnaArgs {
   int direct;                 // 1: taps, W and theta loaded straight into registers (no LDS staging)
   int tiles_per_xcd;          // tiles walked by each XCD
   int nbase_wg;               // 64 * tiles_per_xcd workgroups for the wavelet bases
+  const int32_t *active;      // [C] sub-cubes whose W (mode 1) or theta (mode 2) may change; null: all
 };
 
 // One wavelet basis at one level of the synthesis (levels >= 2): writes the
@@ -105,6 +106,7 @@ struct SynFinalArgs {
   double inv_kappa;
   int64_t I, dirac_row;       // coefficient rows per sub-cube; first row of the Dirac band
   int64_t theta_bytes;        // C * I * 4 (< 2^31)
+  const int32_t *active;      // [C] sub-cubes whose Dirac rows the fused update may change; null: all
   float alpha, beta;
   int ny, nx, L, Lcp, C, Lc, tk, ty, strips, yblocks;
   int y_begin, y_end, x_begin, x_end;  // output pixels computed (all unless per facet)
@@ -136,6 +138,7 @@ struct NucArgs {
   int mode;                  // 0: dual update; 1: weights only
   int q0;                    // first spatial facet of the launch (blockIdx.y offset)
   int eig_q;                 // -1: eig over all C*Q facets; else facets c*Q + eig_q, c < C
+  const int32_t *active;     // [C] sub-cubes whose P (mode 0) or theta_bar (mode 1) may change; null: all
 };
 
 struct GatherArgs {
@@ -152,12 +155,13 @@ struct ClosureArgs {
   float *x, *xcheck, *v;
   const float *y, *grad;
   const double *eps;   // [L] l2-ball radii
-  double *part;        // [nblocks][max(L, 2)] block partial sums (workspace)
+  double *part;        // [nblocks][2 L] block partial sums per channel (workspace)
   double *factor;      // [L] dual scale factors (workspace)
-  double *xi;          // one double: relative variation of this iteration
+  double *xi;          // [C] relative variation of each sub-cube in this iteration
+  const int32_t *active;  // [C] sub-cubes whose x, xcheck, v may change; null: all
   double tau;
   int64_t npix, ppb;   // pixels, pixels per block
-  int L, nblocks;
+  int L, C, nblocks;
 };
 
 struct SnrArgs {
@@ -183,6 +187,16 @@ int launch_nuc_recon(const NucArgs &a, int nspatial, void *stream);
 int launch_nuc_gather(const GatherArgs &a, void *stream);
 int launch_closure(const ClosureArgs &a, void *stream);
 int launch_snr(const SnrArgs &a, void *stream);
+
+// Compute sequences shared by the entry points.  `active` ([C] int32 device
+// flags, or null for all) restricts every state write to the sub-cubes whose
+// flag is set: the other sub-cubes keep their P, W, theta, theta_bar (and, in
+// the closure, x, xcheck, v) bit for bit.
+int facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, float *w, const float *theta,
+                    const double *theta_bar, const double *mu, const double *mu_bar, double zeta, double kappa,
+                    float *grad, void *stream, const int32_t *active);
+int reweight(const fhs_plan *p, const float *x, const double *upsilon, const double *upsilon_bar, float *theta,
+             double *theta_bar, void *stream, const int32_t *active);
 
 }  // namespace fhs
 
@@ -211,7 +225,7 @@ struct fhs_plan {
   int ntap[fhs::kBases];
   // workspace layout (bytes)
   int64_t ws_ll[fhs::kBases][fhs::kMaxLevels];
-  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_red = 0, ws_factor = 0, ws_ctl = 0, ws_bytes = 0;
+  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_red = 0, ws_factor = 0, ws_ctl = 0, ws_active = 0, ws_bytes = 0;
   int64_t red_ppb = 0;                     // closure: pixels per block
   int red_blocks = 0;                      // closure: blocks
   int gram_chunks = 0, max_rows = 0;       // Gram partial slots per facet (workspace capacity)

@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(256) nuc_eig_kernel(NucArgs A) {
     if (A.mode == 0) {
       const double t = A.mu_bar[f] * A.inv_zeta * A.theta_bar[static_cast<int64_t>(f) * n + rk];
       hv[tid] = sig > 0.0 ? fmin(1.0, t / sig) : 1.0;
-    } else {
+    } else if (A.active == nullptr || A.active[F.c] != 0) {  // frozen sub-cubes keep theta_bar
       const double ub = A.mu_bar[f];
       A.theta_bar_out[static_cast<int64_t>(f) * n + rk] = ub / (sig + ub);
     }
@@ -417,6 +417,7 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
     // contiguous runs of S x L_c floats per sub-cube, written in place into P
     const int nfl = sg.n * Lc;
     for (int c = 0; c < C; ++c) {
+      if (A.active != nullptr && A.active[c] == 0) continue;  // a frozen sub-cube keeps its P
       float *dst = A.p + c * g.p_sub + F.poff + (static_cast<int64_t>(sg.y) * F.hx + sg.s0) * Lc;
       for (int e = threadIdx.x; e < nfl; e += blockDim.x) dst[e] = outt[c * S * Lc + e];
     }
@@ -454,6 +455,7 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   const int y0 = chunk * A.chunk_wrows;
   if (y0 >= F.hy) return;
   const int y1 = min(y0 + A.chunk_wrows, F.hy);
+  if (A.active != nullptr && A.active[0] == 0) return;  // the one sub-cube is frozen: P stays
   const int S = A.seg, L = g.L, Lc = g.Lc;
   const int Lp = recon1_stride(L);
   const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;

@@ -21,7 +21,7 @@ struct fhs_graph {
 namespace {
 
 int closure(const fhs_plan *p, float *x, float *xcheck, float *v, const float *y, const double *eps,
-            const float *grad, double tau, double *xi, void *stream) {
+            const float *grad, double tau, double *xi, void *stream, const int32_t *active = nullptr) {
   ClosureArgs a{};
   a.x = x;
   a.xcheck = xcheck;
@@ -32,10 +32,12 @@ int closure(const fhs_plan *p, float *x, float *xcheck, float *v, const float *y
   a.part = reinterpret_cast<double *>(static_cast<char *>(p->ws) + p->ws_red);
   a.factor = reinterpret_cast<double *>(static_cast<char *>(p->ws) + p->ws_factor);
   a.xi = xi;
+  a.active = active;
   a.tau = tau;
   a.npix = static_cast<int64_t>(p->cfg.ny) * p->cfg.nx;
   a.ppb = p->red_ppb;
   a.L = p->L;
+  a.C = p->C;
   a.nblocks = p->red_blocks;
   prof_begin(p, FHS_K_CLOSURE, stream);
   const int rc = launch_closure(a, stream);
@@ -50,6 +52,14 @@ int check_state(const fhs_pdfb_state *s) {
     return fail(FHS_EINVAL, "PDFB state: null array");
   if (!(s->tau > 0)) return fail(FHS_EINVAL, "tau must be positive");
   return FHS_OK;
+}
+
+// One PDFB iteration; xi[c] receives the relative variation of sub-cube c.
+int iteration(const fhs_plan *p, const fhs_pdfb_state *s, double *xi, void *stream, const int32_t *active) {
+  if (int rc = facet_prox_step(p, s->xcheck, s->p, s->w, s->theta, s->theta_bar, s->mu, s->mu_bar, s->zeta, s->kappa,
+                               s->grad, stream, active))
+    return rc;
+  return closure(p, s->x, s->xcheck, s->v, s->y, s->eps, s->grad, s->tau, xi, stream, active);
 }
 
 // Per-channel sums of r^2 and (r - x)^2 into the workspace's control slot,
@@ -105,17 +115,17 @@ int fhs_snr(const fhs_plan *p, const float *x_ref, const float *x, const double 
 }
 
 int fhs_pdfb_iteration(const fhs_plan *p, const fhs_pdfb_state *s, int32_t iter, void *stream) {
+  if (!p) return fail(FHS_EINVAL, "null plan");
+  if (!p->ws) return fail(FHS_ENOWORKSPACE, "no workspace attached (fhs_plan_set_workspace)");
   if (int rc = check_state(s)) return rc;
   if (iter < 0) return fail(FHS_EINVAL, "iteration index must be >= 0");
-  if (int rc = fhs_facet_prox_step(p, s->xcheck, s->p, s->w, s->theta, s->theta_bar, s->mu, s->mu_bar, s->zeta,
-                                   s->kappa, s->grad, stream))
-    return rc;
-  return closure(p, s->x, s->xcheck, s->v, s->y, s->eps, s->grad, s->tau, s->xi + iter, stream);
+  if (!(s->zeta > 0) || !(s->kappa > 0)) return fail(FHS_EINVAL, "zeta and kappa must be positive");
+  return iteration(p, s, s->xi + static_cast<int64_t>(iter) * p->C, stream, nullptr);
 }
 
 int fhs_reweighting_solve(const fhs_plan *p, const fhs_pdfb_state *s, const double *upsilon,
                           const double *upsilon_bar, float *x_prev, const fhs_solve_params *prm, int32_t *iters,
-                          fhs_solve_report *report, void *stream) {
+                          double *rw_xi, fhs_solve_report *report, void *stream) {
   if (!p) return fail(FHS_EINVAL, "null plan");
   if (!p->ws) return fail(FHS_ENOWORKSPACE, "no workspace attached (fhs_plan_set_workspace)");
   if (int rc = check_state(s)) return rc;
@@ -124,57 +134,100 @@ int fhs_reweighting_solve(const fhs_plan *p, const fhs_pdfb_state *s, const doub
     return fail(FHS_EINVAL, "reweighting solve: need max_reweights >= 0 and 1 <= max_iter, min_iter <= max_iter");
   if (!(prm->rw_tol >= 0) || !(prm->pdfb_tol >= 0) || !(prm->res_factor > 0))
     return fail(FHS_EINVAL, "reweighting solve: tolerances must be >= 0 and res_factor > 0");
+  if (!(s->zeta > 0) || !(s->kappa > 0)) return fail(FHS_EINVAL, "zeta and kappa must be positive");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int L = p->L;
+  const int L = p->L, C = p->C;
   const size_t cube_bytes = static_cast<size_t>(p->cfg.ny) * p->cfg.nx * L * sizeof(float);
+  constexpr double kInf = std::numeric_limits<double>::infinity();
   std::vector<double> h(2 * static_cast<size_t>(L));
-  // ||eps||
+  // ||eps_c|| over the channels c, c + C, ... of each sub-cube
   if (hipMemcpyAsync(h.data(), s->eps, sizeof(double) * L, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(FHS_EHIP, "reweighting solve: reading eps failed");
-  double eps2 = 0.0;
-  for (int l = 0; l < L; ++l) eps2 += h[l] * h[l];
-  const double res_bound = prm->res_factor * std::sqrt(eps2);
-  auto sum_of = [&](int k) {
+  std::vector<double> res_bound(C, 0.0);
+  for (int l = 0; l < L; ++l) res_bound[l % C] += h[l] * h[l];
+  for (int c = 0; c < C; ++c) res_bound[c] = prm->res_factor * std::sqrt(res_bound[c]);
+  // per sub-cube: sum over its channels of row k of the channel sums
+  auto sub_sum = [&](int k, int c) {
     double v = 0.0;
-    for (int l = 0; l < L; ++l) v += h[static_cast<size_t>(k) * L + l];
+    for (int l = c; l < L; l += C) v += h[static_cast<size_t>(k) * L + l];
     return v;
   };
   float *theta = const_cast<float *>(s->theta);
   double *theta_bar = const_cast<double *>(s->theta_bar);
-  fhs_solve_report rep{0, 0, std::numeric_limits<double>::infinity(), std::numeric_limits<double>::infinity(),
-                       std::numeric_limits<double>::infinity()};
-  double rw_xi = std::numeric_limits<double>::infinity();
-  for (int t = 0; t < prm->max_reweights && rw_xi > prm->rw_tol; ++t) {
-    if (int rc = fhs_reweight(p, s->x, upsilon, upsilon_bar, theta, theta_bar, stream)) return rc;
+  // Activity flags on the device: the kernels of a pass or an iteration
+  // change only the sub-cubes still running (the others keep their state
+  // bit for bit).  Uploaded when they change; the loop synchronises every
+  // iteration, so the host copy is never rewritten while a copy is pending.
+  int32_t *d_active = reinterpret_cast<int32_t *>(static_cast<char *>(p->ws) + p->ws_active);
+  std::vector<int32_t> act(C, 0), uploaded(C, -1);
+  auto upload = [&]() -> int {
+    if (act == uploaded) return FHS_OK;
+    if (hipMemcpyAsync(d_active, act.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, st) != hipSuccess)
+      return fail(FHS_EHIP, "reweighting solve: uploading the sub-cube flags failed");
+    uploaded = act;
+    return FHS_OK;
+  };
+  std::vector<int32_t> outer(C, prm->max_reweights > 0 ? 1 : 0), pc(C, 0);
+  std::vector<double> xi_c(C, kInf), res_c(C, 0.0), rw_c(C, kInf);
+  std::vector<double> xi_h(C);
+  fhs_solve_report rep{0, 0};
+  if (iters)
+    for (int64_t i = 0; i < static_cast<int64_t>(prm->max_reweights) * C; ++i) iters[i] = 0;
+  if (rw_xi)
+    for (int64_t i = 0; i < static_cast<int64_t>(prm->max_reweights) * C; ++i) rw_xi[i] = kInf;
+  auto any = [](const std::vector<int32_t> &v) {
+    for (int32_t e : v)
+      if (e) return true;
+    return false;
+  };
+  // Alg. 1 for every sub-cube c (its own pass counter t_c and relative
+  // variation); the sub-cubes still in their loop advance together, one pass
+  // at a time, so pass t is pass t of each of them.
+  for (int t = 0; any(outer); ++t) {
+    act = outer;
+    if (int rc = upload()) return rc;
+    if (int rc = reweight(p, s->x, upsilon, upsilon_bar, theta, theta_bar, stream, d_active)) return rc;
     if (hipMemcpyAsync(x_prev, s->x, cube_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemcpyAsync(s->xcheck, s->x, cube_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
       return fail(FHS_EHIP, "reweighting solve: device copy failed");
-    // Alg. 2 from X(t): r of the iterate entering each iteration
-    if (int rc = channel_sums(p, s->y, s->x, h.data(), st)) return rc;
-    double res = std::sqrt(sum_of(1)), xi = std::numeric_limits<double>::infinity();
-    int32_t it = 0;
-    while (it < prm->min_iter || (it < prm->max_iter && (xi > prm->pdfb_tol || res > res_bound))) {
-      if (it > 0)
-        if (int rc = channel_sums(p, s->y, s->x, h.data(), st)) return rc;
-      res = std::sqrt(sum_of(1));
-      if (int rc = fhs_pdfb_iteration(p, s, it, stream)) return rc;
-      if (hipMemcpyAsync(&xi, s->xi + it, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+    // Alg. 2 from X_c(t) for each running sub-cube: its own p, xi_c and the
+    // residual r_c of the iterate entering each iteration
+    for (int c = 0; c < C; ++c) {
+      pc[c] = 0;
+      xi_c[c] = kInf;
+    }
+    for (int32_t it = 0; any(act); ++it) {
+      if (int rc = channel_sums(p, s->y, s->x, h.data(), st)) return rc;
+      for (int c = 0; c < C; ++c)
+        if (act[c]) res_c[c] = std::sqrt(sub_sum(1, c));
+      if (int rc = upload()) return rc;
+      double *xi_dev = s->xi + static_cast<int64_t>(it) * C;
+      if (int rc = iteration(p, s, xi_dev, stream, d_active)) return rc;
+      if (hipMemcpyAsync(xi_h.data(), xi_dev, sizeof(double) * C, hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)
         return fail(FHS_EHIP, "reweighting solve: reading xi failed");
-      ++it;
+      for (int c = 0; c < C; ++c) {
+        if (!act[c]) continue;
+        xi_c[c] = xi_h[c];
+        ++pc[c];
+        ++rep.iterations;
+        act[c] = pc[c] < prm->min_iter ||
+                 (pc[c] < prm->max_iter && (xi_c[c] > prm->pdfb_tol || res_c[c] > res_bound[c]));
+      }
     }
-    if (iters) iters[t] = it;
-    rep.iterations += it;
-    rep.last_xi = xi;
-    rep.last_res = res;
-    // relative variation between reweights
+    // relative variation of each sub-cube between reweights
     if (int rc = channel_sums(p, x_prev, s->x, h.data(), st)) return rc;
-    const double n0 = sum_of(0);
-    rw_xi = n0 > 0.0 ? std::sqrt(sum_of(1) / n0) : std::numeric_limits<double>::infinity();
+    for (int c = 0; c < C; ++c) {
+      if (!outer[c]) continue;
+      const double n0 = sub_sum(0, c);
+      rw_c[c] = n0 > 0.0 ? std::sqrt(sub_sum(1, c) / n0) : kInf;
+      if (iters) iters[static_cast<int64_t>(t) * C + c] = pc[c];
+      if (rw_xi) rw_xi[static_cast<int64_t>(t) * C + c] = rw_c[c];
+      outer[c] = t + 1 < prm->max_reweights && rw_c[c] > prm->rw_tol;
+    }
     rep.runs = t + 1;
   }
-  rep.rw_xi = rw_xi;
   if (report) *report = rep;
   return FHS_OK;
 }

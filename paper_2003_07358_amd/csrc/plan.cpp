@@ -44,7 +44,7 @@ using namespace fhs;
 
 extern "C" {
 
-int fhs_version(void) { return 100; }
+int fhs_version(void) { return 200; }
 
 const char *fhs_last_error(void) { return g_err.c_str(); }
 
@@ -255,6 +255,9 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   // per-channel sums read back by the reweighting solve
   p->ws_ctl = ws;
   ws = align256(ws + static_cast<int64_t>(p->L) * 2 * 8);
+  // per-sub-cube activity flags of the reweighting solve
+  p->ws_active = ws;
+  ws = align256(ws + static_cast<int64_t>(p->C) * 4);
   p->ws_bytes = ws;
   *out = p;
   return FHS_OK;

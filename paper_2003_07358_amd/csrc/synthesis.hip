@@ -423,6 +423,8 @@ syn_final_kernel(SynFinalArgs A) {
   // Dirac arithmetic, operation for operation), stored, and enters the output.
   const bool fuse = FIRST && A.xin != nullptr;
   const float thr = fuse ? static_cast<float>(A.mu[c] * A.inv_kappa) : 0.0f;
+  // a frozen sub-cube keeps its Dirac rows (the old value is stored back)
+  const bool act = !fuse || A.active == nullptr || A.active[c] != 0;
   // theta word of this lane's two pixels in a row run starting at column 2 kx0
   int vt[2];
 #pragma unroll
@@ -519,7 +521,8 @@ syn_final_kernel(SynFinalArgs A) {
               const __amdgpu_buffer_rsrc_t rd = run(A.dirac, 2 * kp + py);
 #pragma unroll
               for (int px = 0; px < 2; ++px) {
-                wd[px] = l21_row_update(vcur[k][py][px], xcur[k][py][px], thr * tcur[k][py][px], Lcp);
+                const float nw = l21_row_update(vcur[k][py][px], xcur[k][py][px], thr * tcur[k][py][px], Lcp);
+                wd[px] = act ? nw : vcur[k][py][px];
                 st_f32s(wd[px], rd, vd[px]);
               }
             }

@@ -140,7 +140,7 @@ def test_cfg4_graph_50_iterations():
                  w=torch.zeros(s["n_w"], dtype=torch.float32, device="cuda"),
                  v=torch.zeros(s["n_x"], dtype=torch.float32, device="cuda"),
                  grad=torch.empty(s["n_x"], dtype=torch.float32, device="cuda"),
-                 xi=torch.zeros(n, dtype=torch.float64, device="cuda"))
+                 xi=torch.zeros(n * w.C, dtype=torch.float64, device="cuda"))
         return t, plan.pdfb_state(**t, **const)
 
     te, ste = fresh()

@@ -57,17 +57,17 @@ def test_closure_parity(name):
     C = next(c for c in range(1, L + 1) if L % c == 0 and L // c <= 64)
     plan = fhs.Plan(ny, nx, L, n_sub=C, levels=1 if min(ny, nx) < 16 else 4).attach_workspace()
     xt, xct, vt = dev(x), dev(xc), dev(v)
-    xi = torch.zeros(1, dtype=torch.float64, device="cuda")
+    xi = torch.zeros(C, dtype=torch.float64, device="cuda")
     plan.pdfb_closure(xt, xct, vt, dev(y), dev(eps), dev(g), 0.33, xi)
     vr = closure.data_dual_update(v, xc, y, eps)
-    xr, xcr, xir = closure.primal_update(x, g, vr, 0.33)
+    xr, xcr, xir = closure.primal_update(x, g, vr, 0.33, C)
     for nm, got, ref in (("v", host(vt), vr), ("x", host(xt), xr), ("xcheck", host(xct), xcr)):
         e = rel_l2(got, ref)
         log(f"    {nm}: rel_l2={e:.3e}")
         assert e <= 1e-6, (nm, e)
-    xig = float(host(xi)[0])
-    log(f"    xi gpu={xig:.12e} oracle={xir:.12e}")
-    assert abs(xig - xir) <= 1e-12 * xir + 1e-15
+    xig = host(xi)
+    log(f"    xi (C={C}) gpu={xig[:4]} oracle={xir[:4]}")
+    np.testing.assert_allclose(xig, xir, rtol=1e-12, atol=1e-15)
 
 
 def pdfb_problem(ny, nx, L, qy, qx, C, o, levels=4, seed=0, blobs=12, frac=0.05):
@@ -83,7 +83,7 @@ def gpu_state(plan, pb, y, eps, x0, n_xi):
              v=torch.zeros(x0.size, dtype=torch.float32, device="cuda"), y=dev(y), eps=dev(eps),
              theta=dev(pb.theta_flat()), theta_bar=dev(pb.theta_bar_flat()), mu=dev(pb.mu),
              mu_bar=dev(pb.mu_bar_flat()), grad=torch.empty(x0.size, dtype=torch.float32, device="cuda"),
-             xi=torch.zeros(n_xi, dtype=torch.float64, device="cuda"))
+             xi=torch.zeros(n_xi * pb.C, dtype=torch.float64, device="cuda"))
     return t, plan.pdfb_state(**t)
 
 
@@ -120,9 +120,9 @@ def test_pdfb_iterations_parity(name):
                 e = rel_l2(got[n].reshape(-1), ref[n].reshape(-1))
             log(f"    it {k} {n}: rel err={e:.3e}")
             assert e <= k * 1e-5, (k, n, e)
-        xig = float(host(t["xi"])[k - 1])
-        log(f"    it {k} xi gpu={xig:.6e} oracle={xi:.6e}")
-        assert abs(xig - xi) <= 2 * k * 1e-5
+        xig = host(t["xi"])[(k - 1) * pb.C:k * pb.C]
+        log(f"    it {k} xi gpu={xig} oracle={xi}")
+        assert np.all(np.abs(xig - xi) <= 2 * k * 1e-5)
 
 
 def test_pdfb_graph_replays_match_eager():
@@ -153,49 +153,63 @@ def test_pdfb_graph_replays_match_eager():
 
 
 SOLVE_CASES = {
-    # (case, x0, T, rw_tol, p_min, p_max, pdfb_tol, res_factor): runs that stop
-    # on the relative variation, on the residual, and at the caps; the
-    # deciding values are far from the bounds (checked on the oracle side)
-    "xi_stop": ("q2x2_c2_64x64x12", "zero", 2, 0.0, 2, 12, 0.1, 1.01),
-    "res_stop": ("q3x2_c1_90x70x8", "zero", 2, 0.0, 2, 12, 1.0, 1.01),
-    "caps": ("q3x2_c1_90x70x8", "data", 2, 0.0, 2, 3, 0.0, 1.01),
-    "outer_stop": ("q2x2_c2_64x64x12", "data", 3, 1.0, 1, 2, 0.0, 1.01),
+    # (case, x0, T, rw_tol, p_min, p_max, pdfb_tol, res_factor, zero_sub, eps_scale): runs that stop on
+    # the relative variation, on the residual, and at the caps; sub-cubes that
+    # stop at different iterations and passes (a zero sub-cube runs to the cap
+    # beside a noisy one; unequal ball radii per sub-cube); the deciding values
+    # are far from the bounds (checked on the oracle side)
+    "xi_stop": ("q2x2_c2_64x64x12", "zero", 2, 0.0, 2, 12, 0.1, 1.01, None, None),
+    "res_stop": ("q3x2_c1_90x70x8", "zero", 2, 0.0, 2, 12, 1.0, 1.01, None, None),
+    "caps": ("q3x2_c1_90x70x8", "data", 2, 0.0, 2, 3, 0.0, 1.01, None, None),
+    "outer_stop": ("q2x2_c2_64x64x12", "data", 3, 1.0, 1, 2, 0.0, 1.01, None, None),
+    "zero_subcube": ("q2x2_c2_64x64x12", "data", 2, 0.0, 2, 14, 2e-2, 1.01, 0, None),
+    "radii_per_subcube": ("q2x2_c2_64x64x12", "data", 1, 0.0, 2, 16, 2e-2, 1.01, None, (3.0, 1e-3)),
+    "outer_per_subcube": ("q2x2_c2_64x64x12", "data", 3, 10.0, 2, 3, 0.0, 1.01, 0, None),
 }
 
 
 @pytest.mark.parametrize("name", list(SOLVE_CASES))
 def test_reweighting_solve_parity(name):
-    """Alg. 1 on the GPU (fhs_reweighting_solve) against the oracle's loop:
-    the same number of runs and iterations per run, and the state after K
-    iterations in all within K * 1e-5 (as for K plain iterations), the weights
-    of the last pass included."""
+    """Alg. 1 on the GPU (fhs_reweighting_solve) against the oracle's loops,
+    one per sub-cube: the same number of runs and iterations per run for
+    every sub-cube, and the state after K iterations in all within K * 1e-5
+    (as for K plain iterations), the weights of the last pass included."""
     from oracle import solve
-    case, start, T, rw_tol, p_min, p_max, pdfb_tol, res_factor = SOLVE_CASES[name]
+    case, start, T, rw_tol, p_min, p_max, pdfb_tol, res_factor, zero_sub, eps_scale = SOLVE_CASES[name]
     log(f"[case] reweighting solve {name}: {case} from {start}")
     pb, y, eps, x0 = pdfb_problem(**PDFB_CASES[case])
+    C = pb.C
+    if zero_sub is not None:
+        y = y.copy()
+        y[..., zero_sub::C] = 0.0
+        x0 = np.maximum(y, 0.0).astype(np.float32)
+    if eps_scale is not None:
+        eps = eps * np.array([eps_scale[l % C] for l in range(pb.L)])
     if start == "zero":
         x0 = np.zeros_like(x0)
     kw = dict(T=T, xi_rw=rw_tol, p_min=p_min, p_max=p_max, xi_tol=pdfb_tol, res_factor=res_factor)
     x, P, W, v, th, thb, rep = solve.reweighting_solve(x0, pb.P, pb.W, np.zeros(x0.shape), y, eps, pb.mu, pb.mu_bar,
-                                                       pb.mu, pb.mu_bar, pb.geom, C=pb.C, levels=pb.levels, **kw)
-    iters = [len(h) for h in rep["runs"]]
+                                                       pb.mu, pb.mu_bar, pb.geom, C=C, levels=pb.levels, **kw)
+    iters = [[len(h) for h in rep["runs"][c]] for c in range(C)]
     # every stopping decision of the oracle is taken with a wide margin
-    bound = res_factor * np.linalg.norm(eps)
-    for h in rep["runs"]:
-        for xi, r in h:
-            assert pdfb_tol == 0.0 or np.isinf(xi) or abs(xi / pdfb_tol - 1.0) > 0.05
-            assert abs(r / bound - 1.0) > 0.01
-    assert all(rw_tol == 0.0 or np.isinf(xi) or abs(xi / rw_tol - 1.0) > 0.05 for xi in rep["xi"])
-    log(f"    oracle: iterations per run {iters}, outer xi {rep['xi']}")
+    for c in range(C):
+        bound = res_factor * np.linalg.norm(eps[c::C])
+        for h in rep["runs"][c]:
+            for xi, r in h:
+                assert pdfb_tol == 0.0 or np.isinf(xi) or abs(xi / pdfb_tol - 1.0) > 0.05
+                assert abs(r / bound - 1.0) > 0.01
+        assert all(rw_tol == 0.0 or np.isinf(xi) or abs(xi / rw_tol - 1.0) > 0.05 for xi in rep["xi"][c])
+    log(f"    oracle: iterations per run and sub-cube {iters}, outer xi {rep['xi']}")
 
     plan = fhs.Plan(*pb.cfg).attach_workspace()
     t, st = gpu_state(plan, pb, y, eps, x0, p_max)
     x_prev = torch.empty(x0.size, dtype=torch.float32, device="cuda")
     got = plan.reweighting_solve(st, dev(pb.mu), dev(pb.mu_bar_flat()), x_prev, max_reweights=T, rw_tol=rw_tol,
                                  min_iter=p_min, max_iter=p_max, pdfb_tol=pdfb_tol, res_factor=res_factor)
-    log(f"    gpu:    iterations per run {got['iters']}, outer xi {got['rw_xi']:.6e}")
-    assert got["iters"] == iters and got["runs"] == len(iters) and got["iterations"] == sum(iters)
-    K = sum(iters)
+    log(f"    gpu:    iterations per run and sub-cube {got['iters']}, outer xi {got['rw_xi']}")
+    assert got["iters"] == iters and got["runs"] == max(len(i) for i in iters)
+    assert got["iterations"] == sum(sum(i) for i in iters)
+    K = max(sum(i) for i in iters)
     ref = {"x": x, "p": np.concatenate([q.reshape(-1) for row in P for q in row]), "w": np.concatenate(W, axis=1),
            "theta": np.concatenate(th), "theta_bar": np.concatenate([q for row in thb for q in row])}
     for n, r in ref.items():
@@ -205,8 +219,13 @@ def test_reweighting_solve_parity(name):
     ev = np.linalg.norm(host(t["v"]).reshape(-1) - v.reshape(-1)) / np.linalg.norm(y)
     log(f"    v: err / ||y|| = {ev:.3e}")
     assert ev <= K * 1e-5
-    xo = rep["xi"][-1]
-    assert (np.isinf(xo) and np.isinf(got["rw_xi"])) or abs(got["rw_xi"] - xo) <= 1e-3 * xo
+    if zero_sub is not None:
+        # the zero sub-cube stays exactly zero throughout
+        xg = host(t["x"]).reshape(x0.shape)
+        assert not np.any(xg[..., zero_sub::C])
+    for c in range(C):
+        for a, b in zip(got["rw_xi"][c], rep["xi"][c]):
+            assert (np.isinf(a) and np.isinf(b)) or abs(a - b) <= 1e-3 * b
 
 
 def test_resume_from_checkpoint_is_bitwise(tmp_path):
