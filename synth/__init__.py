@@ -116,3 +116,53 @@ def noisy_data(X, frac, seed):
     sigma = frac * float(np.max(np.abs(X)))
     n = rng(seed).standard_normal(X.shape)
     return (X.astype(np.float64) + sigma * n).astype(np.float32), sigma
+
+
+# ---------------------------------------------------------------- counter-based values
+# Warm duals of full-size problems are too large to draw on the host and ship
+# to the device; instead each value is a fixed function of its index, which
+# the host (numpy) and the device (torch) evaluate identically, so that a
+# sampled block on the host sees exactly the values the device holds.
+
+def hash32(i, j, seed):
+    """32-bit integer hash of (i, j, seed) (T. Mueller's 0x45d9f3b
+    xor-shift-multiply mixer applied to a linear combination of the
+    counters).  i, j: int64 arrays (numpy) or tensors (torch) of values below
+    2^31; every intermediate stays below 2^63.  Returns int64 in [0, 2^32)."""
+    h = (i * 73856093 + j * 19349663 + seed * 83492791) & 0xFFFFFFFF
+    h = ((h ^ (h >> 16)) * 0x45D9F3B) & 0xFFFFFFFF
+    h = ((h ^ (h >> 16)) * 0x45D9F3B) & 0xFFFFFFFF
+    return h ^ (h >> 16)
+
+
+def hash_uniform_np(i, j, seed):
+    """float64 in [-0.5, 0.5) from hash32 (numpy)."""
+    h = hash32(np.asarray(i, dtype=np.int64), np.asarray(j, dtype=np.int64), int(seed))
+    return h.astype(np.float64) / 4294967296.0 - 0.5
+
+
+WARM_W_SEED, WARM_P_SEED = 71, 73
+
+
+def warm_w_np(rows, positions, scale):
+    """Warm l21 dual: W[i, p] = scale * u(i, p), u = hash_uniform(i, p, WARM_W_SEED),
+    rounded once to float32.  rows: coefficient rows, positions: channel
+    positions (broadcast against each other)."""
+    return (float(scale) * hash_uniform_np(rows, positions, WARM_W_SEED)).astype(np.float32)
+
+
+def warm_p_np(facet, n, scale):
+    """Warm nuclear dual of facet f (flattened [ny~][nx~][L_c], n values):
+    P[e] = scale * hash_uniform(e, f, WARM_P_SEED), rounded to float32."""
+    return (float(scale) * hash_uniform_np(np.arange(n, dtype=np.int64), facet, WARM_P_SEED)).astype(np.float32)
+
+
+def warm_w_scale(mu_c):
+    """Amplitude of the warm l21 dual of sub-cube c: rows of norm about the
+    threshold, so that both branches of the row shrink occur."""
+    return 0.8 * float(mu_c)
+
+
+def warm_p_scale(mu_bar_f, n_rows):
+    """Amplitude of the warm nuclear dual of a facet with n_rows pixels."""
+    return 0.3 * float(mu_bar_f) / np.sqrt(n_rows)

@@ -119,3 +119,102 @@ class Problem:
         for ch in step.subcube_channels(self.L, self.C):
             outs.append(sara.flatten(sara.analysis(self.X.astype(np.float64)[..., ch], self.levels)))
         return np.concatenate(outs, axis=1)
+
+
+# ---------------------------------------------------------------- full-size problems on the device
+def fill_warm_duals(plan, p_dev, w_dev, mu, mu_bar, chunk_rows=1 << 20):
+    """Warm duals of a full-size problem written straight into the device
+    arrays with the counter-based generator of `synth` (the sampled-block
+    oracle evaluates the same values on the host)."""
+    import torch
+    s = plan.sizes
+    C, L, Lc = plan.C, plan.L, plan.Lc
+    dev = p_dev.device
+    for f in range(s["n_facets"]):
+        fi = plan.facet(f)
+        rows = (fi["wy1"] - fi["wy0"]) * (fi["wx1"] - fi["wx0"])
+        n = rows * Lc
+        h = synth.hash32(torch.arange(n, dtype=torch.int64, device=dev), f, synth.WARM_P_SEED)
+        u = h.double() / 4294967296.0 - 0.5
+        p_dev[fi["poff"]:fi["poff"] + n] = (synth.warm_p_scale(mu_bar[f], rows) * u).float()
+    I = s["n_coef"]
+    pos = torch.arange(L, dtype=torch.int64, device=dev)
+    scale = torch.tensor([synth.warm_w_scale(mu[p // Lc]) for p in range(L)], dtype=torch.float64, device=dev)
+    wv = w_dev.view(I, L)
+    for r0 in range(0, I, chunk_rows):
+        r1 = min(I, r0 + chunk_rows)
+        rows = torch.arange(r0, r1, dtype=torch.int64, device=dev)
+        h = synth.hash32(rows[:, None], pos[None, :], synth.WARM_W_SEED)
+        wv[r0:r1] = (scale[None, :] * (h.double() / 4294967296.0 - 0.5)).float()
+
+
+def warm_oracle_inputs(geom, C, L, mu, mu_bar):
+    """The same warm duals as callables for oracle.blocks.block_step."""
+    Lc = L // C
+    shapes = sara.band_shapes(geom.ny, geom.nx, geom.levels)
+    offs = np.concatenate([[0], np.cumsum([a * b for a, b in shapes])]).astype(np.int64)
+
+    def P0(c, f):
+        n = f.n_rows * Lc
+        return synth.warm_p_np(c * geom.Q + f.index, n, synth.warm_p_scale(mu_bar[c][f.index], f.n_rows)) \
+            .reshape(f.nuc_shape + (Lc,))
+
+    def W0(rr, cc, k, c):
+        i = offs[k] + rr.astype(np.int64) * shapes[k][1] + cc
+        pos = c * Lc + np.arange(Lc, dtype=np.int64)
+        return synth.warm_w_np(i[..., None], pos, synth.warm_w_scale(mu[c]))
+
+    return P0, W0
+
+
+def random_weight_inputs(geom, C, theta_full, theta_bar_full):
+    """Callables giving the full problem's weights (theta [C][I], theta_bar
+    [C*Q] arrays) at block positions, for oracle.blocks.block_step."""
+    shapes = sara.band_shapes(geom.ny, geom.nx, geom.levels)
+    offs = np.concatenate([[0], np.cumsum([a * b for a, b in shapes])]).astype(np.int64)
+    th = np.asarray(theta_full).reshape(C, -1)
+
+    def theta(rr, cc, k, c):
+        return th[c][offs[k] + rr.astype(np.int64) * shapes[k][1] + cc]
+
+    def theta_bar(c, f):
+        return theta_bar_full[c * geom.Q + f.index]
+
+    return theta, theta_bar
+
+
+def device_block_outputs(plan, p_dev, w_dev, g_dev, geom, blk):
+    """The device results a sampled block determines: P+ of its facets
+    ({(c, q): array}), W+ over the coefficient rectangles its facets own (per
+    band, (rows, cols, L)), G over its exact tiles (rows, cols, L)."""
+    from oracle import blocks
+    C, L, Lc = plan.C, plan.L, plan.Lc
+    P = {}
+    for f in blk.facets(geom):
+        for c in range(C):
+            fi = plan.facet(c * geom.Q + f.index)
+            n = (fi["wy1"] - fi["wy0"]) * (fi["wx1"] - fi["wx0"]) * Lc
+            P[(c, f.index)] = p_dev[fi["poff"]:fi["poff"] + n].cpu().numpy().reshape(f.nuc_shape + (Lc,))
+    bands = plan.bands()
+    assert [(r, c) for r, c, _, _ in bands] == sara.band_shapes(geom.ny, geom.nx, geom.levels)
+    I = plan.sizes["n_coef"]
+    wv = w_dev.view(I, L)
+    W = []
+    for k, ((r0, r1), (c0, c1)) in enumerate(blocks.owned_rects(geom, blk)):
+        rows, cols, off, _ = bands[k]
+        W.append(wv[off:off + rows * cols].view(rows, cols, L)[r0:r1, c0:c1].cpu().numpy())
+    (gy0, gy1), (gx0, gx1) = blocks.exact_tile_rect(geom, blk)
+    G = g_dev.view(geom.ny, geom.nx, L)[gy0:gy1, gx0:gx1].cpu().numpy()
+    return dict(P=P, W=W, G=G)
+
+
+def block_errors(got, ref):
+    """rel_l2 and max_rel of P+, W+, G between device and oracle block results."""
+    keys = sorted(ref["P"])
+    pairs = {
+        "P": (np.concatenate([got["P"][k].reshape(-1) for k in keys]),
+              np.concatenate([ref["P"][k].reshape(-1) for k in keys])),
+        "W": (np.concatenate([g.reshape(-1) for g in got["W"]]), np.concatenate([r.reshape(-1) for r in ref["W"]])),
+        "G": (got["G"].reshape(-1), ref["G"].reshape(-1)),
+    }
+    return {k: (rel_l2(a, b), max_rel(a, b), b.size) for k, (a, b) in pairs.items()}

@@ -1,14 +1,20 @@
-"""Full-size workloads on the GPU, checked against the FP64 oracle on a
-sampled block, and the 50-iteration HIP graph of the batched spectral case.
+"""Full-size workloads on the GPU, checked against the FP64 oracle on sampled
+blocks of facets, and the 50-iteration HIP graph of the batched spectral case.
 
-Sampled parity: the oracle runs the facet step on the top-left 3 x 3 facets
-of the cube (same tile size, overlap and weights).  There it is exact for the
-nuclear duals of the four facets whose right / bottom neighbours lie inside
-the block (their windows and apodization are those of the full problem), for
-the wavelet coefficients at level j with both indices below n_block / 2^j
-(the causal transform reads only lower indices), and for the gradient on the
-first tile (its facets are among those four, and its wavelet support ends
-well inside the block).  Same bar as the other parity tests.
+Sampled parity (oracle/blocks.py): the step is local (Sec. 2.4.2), so the
+oracle computes, on a block of facets and a sub-image reaching E pixels above /
+left of it, exactly what the full problem gives for the block's facets (P+),
+the coefficient rows they own (W+) and the tiles whose right / bottom
+neighbours are in the block or outside the image (G).  Blocks: the top-left
+corner, the bottom-right corner (the last facet: no falling ramp, owns the
+band tails), a right-edge pair, and the 2 x 2 block around the brightest
+pixel.  Inputs: zero duals with random weights (top-left), warm duals (from
+the counter-based generator, identical on host and device) with random
+weights at 2048^2, and at 4096^2 x 64 warm duals with the reweighting weights
+of the cube itself (eqs. facet_hypersara_rank, facet_hypersara_sparsity;
+fhs_reweight on the device, the oracle's own weights on the host).  Same bar as
+the other parity tests: relative L2 <= 1e-5 per output and element-wise
+<= 1e-4 of the largest magnitude.
 """
 import time
 
@@ -16,8 +22,9 @@ import numpy as np
 import pytest
 
 import synth
-from fhs_cases import log, max_rel, rel_l2
-from oracle import closure, geometry, sara, step
+from fhs_cases import (block_errors, device_block_outputs, fill_warm_duals, log, random_weight_inputs,
+                       warm_oracle_inputs)
+from oracle import blocks, closure, geometry
 
 torch = pytest.importorskip("torch")
 fhs = pytest.importorskip("paper_2003_07358_amd")
@@ -31,13 +38,6 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def check(name, got, ref):
-    e, m = rel_l2(got, ref), max_rel(got, ref)
-    log(f"    {name}: rel_l2={e:.3e} max_rel={m:.3e} ({np.asarray(ref).size} values)")
-    assert e <= TOL, (name, e)
-    assert m <= ELEM, (name, m)
-
-
 def full_inputs(w):
     X = synth.workload_cube(w)
     plan = fhs.Plan(w.ny, w.nx, w.L, w.qy, w.qx, w.C, w.overlap, w.overlap, w.levels).attach_workspace()
@@ -49,80 +49,104 @@ def full_inputs(w):
     return X, plan, theta, tbar, mu, mub
 
 
-@pytest.mark.parametrize("wname", ["cfg4_2048x2048x100_c10", "cfg5_4096x4096x64", "cfg3_2048x2048x60"])
-def test_sampled_block_parity(wname):
+def bright_block(X, geom):
+    """2 x 2 block of facets around the brightest pixel (summed over channels)."""
+    iy, ix = np.unravel_index(np.argmax(np.sum(X, axis=2, dtype=np.float64)), X.shape[:2])
+    ty, tx = geometry.tile_bounds(geom.ny, geom.qy), geometry.tile_bounds(geom.nx, geom.qx)
+    sy = int(np.searchsorted(ty, iy, side="right")) - 1
+    sx = int(np.searchsorted(tx, ix, side="right")) - 1
+    return min(max(sy, 0), geom.qy - 2), min(max(sx, 0), geom.qx - 2), 2, 2
+
+
+def block_spec(name, X, geom):
+    if name == "top_left":
+        return 0, 0, 2, 2
+    if name == "bottom_right":
+        return geom.qy - 1, geom.qx - 1, 1, 1
+    if name == "right_edge":
+        return geom.qy // 2 - 1, geom.qx - 1, 2, 1
+    return bright_block(X, geom)
+
+
+# (workload, input variant, block): variant "zero" = zero duals and random
+# weights, "warm" = warm duals and random weights, "reweight" = warm duals and
+# the cube's own reweighting weights
+CASES = [
+    ("cfg3_2048x2048x60", "zero", "top_left"),
+    ("cfg3_2048x2048x60", "warm", "right_edge"),
+    ("cfg3_2048x2048x60", "warm", "bright"),
+    ("cfg4_2048x2048x100_c10", "zero", "top_left"),
+    ("cfg4_2048x2048x100_c10", "warm", "bottom_right"),
+    ("cfg4_2048x2048x100_c10", "warm", "bright"),
+    ("cfg5_4096x4096x64", "zero", "top_left"),
+    ("cfg5_4096x4096x64", "reweight", "bottom_right"),
+    ("cfg5_4096x4096x64", "reweight", "right_edge"),
+    ("cfg5_4096x4096x64", "reweight", "bright"),
+]
+
+_cache = {}
+
+
+def gpu_run(wname, variant):
+    """One facet step of the full workload on the device for an input variant,
+    cached for the blocks that follow (one workload held at a time)."""
+    key = (wname, variant)
+    if key in _cache:
+        return _cache[key]
+    _cache.clear()
+    torch.cuda.empty_cache()
     w = synth.WORKLOADS[wname]
-    log(f"[case] sampled 3x3-facet block parity, {wname}")
+    t0 = time.time()
     X, plan, theta, tbar, mu, mub = full_inputs(w)
     s = plan.sizes
+    x = dev(X)
     p = torch.zeros(s["n_p"], dtype=torch.float32, device="cuda")
     wt = torch.zeros(s["n_w"], dtype=torch.float32, device="cuda")
     g = torch.empty(s["n_x"], dtype=torch.float32, device="cuda")
-    plan.facet_prox_step(dev(X), p, wt, dev(theta), dev(np.concatenate(tbar)), dev(mu), dev(mub), 1.0, 1.0, g)
+    th, tb = dev(theta), dev(np.concatenate(tbar))
+    mu_d, mub_d = dev(mu), dev(mub)
+    if variant != "zero":
+        fill_warm_duals(plan, p, wt, mu, mub)
+    if variant == "reweight":
+        # X^(t) = Xcheck at the start of a run, upsilon = mu, upsilon_bar = mu_bar
+        plan.reweight(x, mu_d, mub_d, th, tb)
+    plan.facet_prox_step(x, p, wt, th, tb, mu_d, mub_d, 1.0, 1.0, g)
     torch.cuda.synchronize()
-    log("    gpu step done")
+    log(f"    {wname} ({variant}): inputs and device step in {time.time() - t0:.1f} s")
+    geom = geometry.Geometry(w.ny, w.nx, w.qy, w.qx, w.overlap, w.overlap, w.levels)
+    _cache[key] = dict(w=w, X=X, plan=plan, theta=theta, tbar=tbar, mu=mu, mub=mub, p=p, wt=wt, g=g, geom=geom)
+    return _cache[key]
 
-    k, C, Lc, L, lev = 3, w.C, w.L // w.C, w.L, w.levels
-    Q = w.qy * w.qx
-    f00 = plan.facet(0)
-    ys, xs = plan.facet((k - 1) * w.qx + (k - 1))["ty1"], plan.facet((k - 1) * w.qx + (k - 1))["tx1"]
-    geom = geometry.Geometry(ys, xs, k, k, w.overlap, w.overlap, lev)
-    full_bands = plan.bands()
-    sub_bands = sara.band_shapes(ys, xs, lev)
-    I_full, I_sub = s["n_coef"], sara.n_coefficients(ys, xs, lev)
-    # theta of the block: the full problem's weight of the same band position
-    th_full = theta.reshape(C, I_full)
-    th_sub = np.zeros((C, I_sub), dtype=np.float32)
-    off_s = 0
-    for (rf, cf, off_f, _), (rs, cs) in zip(full_bands, sub_bands):
-        th_sub[:, off_s:off_s + rs * cs] = th_full[:, off_f:off_f + rf * cf].reshape(C, rf, cf)[:, :rs, :cs] \
-            .reshape(C, -1)
-        off_s += rs * cs
-    full_f = lambda c, sy, sx: c * Q + sy * w.qx + sx
-    tb_sub = [[tbar[full_f(c, q // k, q % k)] for q in range(k * k)] for c in range(C)]
-    mub_sub = [[mub[full_f(c, q // k, q % k)] for q in range(k * k)] for c in range(C)]
-    P0 = [[np.zeros(f.nuc_shape + (Lc,)) for f in geom.facets] for _ in range(C)]
-    W0 = [np.zeros((I_sub, Lc)) for _ in range(C)]
+
+@pytest.mark.parametrize("wname,variant,where", CASES, ids=[f"{a}-{b}-{c}" for a, b, c in CASES])
+def test_sampled_block_parity(wname, variant, where):
+    log(f"[case] sampled block parity {wname} {variant} {where}")
+    r = gpu_run(wname, variant)
+    w, X, plan, geom = r["w"], r["X"], r["plan"], r["geom"]
+    C, Lc = w.C, w.L // w.C
+    mub = np.asarray(r["mub"]).reshape(C, geom.Q)
+    blk = blocks.make_block(geom, *block_spec(where, X, geom))
+    got = device_block_outputs(plan, r["p"], r["wt"], r["g"], geom, blk)
+    kw = {}
+    if variant != "zero":
+        kw["P0"], kw["W0"] = warm_oracle_inputs(geom, C, w.L, r["mu"], mub)
+    if variant != "reweight":
+        kw["theta"], kw["theta_bar"] = random_weight_inputs(geom, C, r["theta"], r["tbar"])
     t0 = time.time()
-    Pn, Wn, G = step.facet_prox_step(X[:ys, :xs], P0, W0, list(th_sub), tb_sub, mu, mub_sub, 1.0, 1.0, geom, C=C)
-    log(f"    oracle on {ys}x{xs}x{L} done in {time.time() - t0:.1f} s")
-
-    # nuclear duals of the interior facets of the block
-    got, ref = [], []
-    for c in range(C):
-        for sy in range(k - 1):
-            for sx in range(k - 1):
-                fi = plan.facet(full_f(c, sy, sx))
-                n = (fi["wy1"] - fi["wy0"]) * (fi["wx1"] - fi["wx0"]) * Lc
-                got.append(p[fi["poff"]:fi["poff"] + n].cpu().numpy())
-                ref.append(Pn[c][sy * k + sx].reshape(-1))
-    check("P+ (interior facets of the block)", np.concatenate(got), np.concatenate(ref))
-
-    # wavelet coefficients below the block's exactness bound
-    got, ref = [], []
-    w2 = wt.view(I_full, L)
-    off_s = 0
-    for (rf, cf, off_f, level), (rs, cs) in zip(full_bands, sub_bands):
-        j = max(level, 0)
-        rv, cv = (ys >> j, xs >> j) if j > 0 else (ys, xs)
-        rv, cv = min(rv, rs), min(cv, cs)
-        got.append(w2[off_f:off_f + rf * cf].view(rf, cf, L)[:rv, :cv].cpu().numpy().reshape(-1, L))
-        blk = np.concatenate([Wn[c][off_s:off_s + rs * cs].reshape(rs, cs, Lc)[:rv, :cv] for c in range(C)],
-                             axis=2)
-        ref.append(blk.reshape(-1, L))
-        off_s += rs * cs
-    check("W+ (exact region of every band)", np.concatenate(got), np.concatenate(ref))
-
-    # gradient on the first tile
-    ty1, tx1 = f00["ty1"], f00["tx1"]
-    gg = g.view(w.ny, w.nx, L)[:ty1, :tx1].cpu().numpy()
-    check("G (first tile)", gg, G[:ty1, :tx1])
+    ref = blocks.block_step(X, geom, blk, C, r["mu"], mub, **kw)
+    log(f"    oracle on block {blk} in {time.time() - t0:.1f} s")
+    for k, (e, m, n) in block_errors(got, ref).items():
+        log(f"    {k}: rel_l2={e:.3e} max_rel={m:.3e} ({n} values)")
+        assert e <= TOL, (k, e)
+        assert m <= ELEM, (k, m)
 
 
 def test_cfg4_graph_50_iterations():
     """2048 x 2048 x 100, 8 x 8 facets x 10 interleaved sub-cubes: 50 PDFB
     iterations (identity data term) as one HIP graph, replayed twice, equal
     bit for bit to 50 eager iterations."""
+    _cache.clear()
+    torch.cuda.empty_cache()
     w = synth.WORKLOADS["cfg4_2048x2048x100_c10"]
     log("[case] cfg4 graph of 50 iterations")
     X, plan, theta, tbar, mu, mub = full_inputs(w)
