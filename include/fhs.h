@@ -222,6 +222,26 @@ int fhs_facet_prox_step_plain(const fhs_plan *plan, const float *xcheck, float *
                               const double *mu, const double *mu_bar, double zeta, double kappa,
                               float *grad, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * step as fhs_facet_prox_step, same arguments and results (bit for bit), but
+ * its scratch is the library's own static device array of
+ * fhs_noalloc_scratch_bytes() bytes (32 MiB; each GPU the library runs on
+ * holds one until the process ends) instead of an attached workspace, so no
+ * workspace needs to be attached and nothing is allocated, by this call or
+ * before it.  Returns FHS_EUNSUPPORTED, without launching anything, when the
+ * plan's workspace (fhs_sizes.workspace_bytes) exceeds the scratch.  Every
+ * call on one GPU shares that GPU's scratch: calls that overlap in time on
+ * one GPU race (serialise them, e.g. on one stream).  The scratch keeps the
+ * previous call's contents; the step writes every scratch word before it
+ * reads it, so nothing needs clearing. */
+int fhs_facet_prox_step_noalloc(const fhs_plan *plan, const float *xcheck, float *p_inout,
+                                float *w_inout, const float *theta, const double *theta_bar,
+                                const double *mu, const double *mu_bar, double zeta, double kappa,
+                                float *grad, void *stream);
+/* Bytes of the static scratch of fhs_facet_prox_step_noalloc (host call). */
+int64_t fhs_noalloc_scratch_bytes(void);
+
 /* Reweighting weights from the previous iterate X^(t) (Alg. 1,
  * weight updates):
  *   theta_bar_{f,j} = upsilon_bar_f / (s_j(D_q S~_q X_c) + upsilon_bar_f)  (eq. facet_hypersara_rank)

@@ -83,6 +83,11 @@ SYMBOLS = {
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_facet_prox_step_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                                   ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_noalloc_scratch_bytes": (ctypes.c_int64, []),
     "fhs_reweight": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fhs_snr": (ctypes.c_int, [ctypes.c_void_p] * 7),
@@ -308,6 +313,21 @@ class Plan:
         s = self.sizes
         fn = self._lib.fhs_facet_prox_step_plain if plain else self._lib.fhs_facet_prox_step
         _check(fn(
+            self._p, self._t(xcheck, s["n_x"], torch.float32, "xcheck"),
+            self._t(p, s["n_p"], torch.float32, "p"), self._t(w, s["n_w"], torch.float32, "w"),
+            self._t(theta, s["n_theta"], torch.float32, "theta"),
+            self._t(theta_bar, s["n_theta_bar"], torch.float64, "theta_bar"),
+            self._t(mu, self.C, torch.float64, "mu"),
+            self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"), float(zeta), float(kappa),
+            self._t(grad, s["n_x"], torch.float32, "grad"), _stream(xcheck)))
+
+    def facet_prox_step_noalloc(self, xcheck, p, w, theta, theta_bar, mu, mu_bar, zeta, kappa, grad):
+        """fhs_facet_prox_step_noalloc: the step on the library's static device
+        scratch (no workspace needed; plans whose workspace exceeds the
+        scratch are rejected)."""
+        import torch
+        s = self.sizes
+        _check(self._lib.fhs_facet_prox_step_noalloc(
             self._p, self._t(xcheck, s["n_x"], torch.float32, "xcheck"),
             self._t(p, s["n_p"], torch.float32, "p"), self._t(w, s["n_w"], torch.float32, "w"),
             self._t(theta, s["n_theta"], torch.float32, "theta"),

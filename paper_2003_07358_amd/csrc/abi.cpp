@@ -23,8 +23,10 @@ constexpr int kCUs = 256;                              // compute units of an MI
 
 int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
-float *ws_f(const fhs_plan *p, int64_t off) { return reinterpret_cast<float *>(static_cast<char *>(p->ws) + off); }
-double *ws_d(const fhs_plan *p, int64_t off) { return reinterpret_cast<double *>(static_cast<char *>(p->ws) + off); }
+float *ws_f(const fhs_plan *p, int64_t off) { return reinterpret_cast<float *>(static_cast<char *>(ws_base(p)) + off); }
+double *ws_d(const fhs_plan *p, int64_t off) {
+  return reinterpret_cast<double *>(static_cast<char *>(ws_base(p)) + off);
+}
 
 bool dense_width_h(int lcp) { return (lcp & (lcp - 1)) != 0; }
 bool dense_lanes(const fhs_plan *p) { return dense_width_h(p->Lcp); }

@@ -197,6 +197,9 @@ int facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, float 
                     float *grad, void *stream, const int32_t *active);
 int reweight(const fhs_plan *p, const float *x, const double *upsilon, const double *upsilon_bar, float *theta,
              double *theta_bar, void *stream, const int32_t *active);
+// Workspace base of the compute sequences: the plan's, or the static scratch
+// while fhs_facet_prox_step_noalloc runs on this thread.
+void *ws_base(const fhs_plan *p);
 
 }  // namespace fhs
 
