@@ -201,6 +201,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights", choices=("reweight", "random"), default="reweight",
                     help="reweight: theta, theta_bar from the cube (fhs_reweight); random: U(0.5, 1)")
+    ap.add_argument("--precision", choices=("fp32", "mixed"), default="fp32",
+                    help="fp32: filters, Gram and reconstruction accumulated in FP64 (default); mixed: the "
+                         "l21 filters in FP32 and the Gram on BF16 MFMA (FHS_PRECISION_MIXED)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default launch shapes")
     ap.add_argument("--form", choices=("batched", "plain"), default="batched",
                     help="batched: every operator one launch over all facets (default); plain: the "
@@ -236,7 +239,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    plan = fhs.Plan(w.ny, w.nx, w.L, w.qy, w.qx, w.C, w.overlap, w.overlap, w.levels).attach_workspace()
+    mixed = args.precision == "mixed"
+    plan = fhs.Plan(w.ny, w.nx, w.L, w.qy, w.qx, w.C, w.overlap, w.overlap, w.levels,
+                    precision=1 if mixed else 0).attach_workspace()
     s = plan.sizes
     mu, mub = plan.heuristics(synth.sigma_bar(X))
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -249,6 +254,18 @@ def main():
         seed = synth.BASE_SEED + w.seed_offset
         th_d = dev(synth.uniform_weights(s["n_theta"], seed + 11))
         tb_d = dev(np.concatenate([synth.sorted_weights(plan.Lc, seed + 100 + f) for f in range(s["n_facets"])]))
+    kappa_hist = None
+    if mixed and args.weights == "reweight":
+        # kappa_q = s_1(Z_q) / min_j t_j of every facet at the first step (Z = D_q Xcheck): with
+        # upsilon_bar = mu_bar, theta_bar_1 = mu_bar / (s_1 + mu_bar) and t_min = mu_bar theta_bar_1,
+        # so kappa = (1 / theta_bar_1 - 1) / theta_bar_1 (from the FP64 weights)
+        tb1 = tb_d.view(s["n_facets"], plan.Lc)[:, 0].cpu().numpy()
+        kappa = (1.0 / tb1 - 1.0) / tb1
+        edges = [0.0, 1.0, 2.0, 3.0, 4.0, 5.0, 6.0, np.inf]
+        counts, _ = np.histogram(np.log10(np.maximum(kappa, 1e-300)), bins=edges)
+        kappa_hist = {"log10_kappa_bin_edges": edges[:-1] + ["inf"], "facets": counts.tolist(),
+                      "min": float(kappa.min()), "median": float(np.median(kappa)), "max": float(kappa.max())}
+        log(f"[bench] kappa per facet: min {kappa.min():.3e} median {np.median(kappa):.3e} max {kappa.max():.3e}")
     p_d = torch.zeros(s["n_p"], dtype=torch.float32, device="cuda")
     w_d = torch.zeros(s["n_w"], dtype=torch.float32, device="cuda")
     g_d = torch.empty(s["n_x"], dtype=torch.float32, device="cuda")
@@ -337,16 +354,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (filters, Gram and reconstruction accumulated in f64)",
+        "dtype": ("f32 / bf16 (l21 filters accumulated in f32; Gram bf16 on MFMA, f32 accumulation; eig and "
+                  "reconstruction f64)" if mixed else "f32 (filters, Gram and reconstruction accumulated in f64)"),
         "data": "synthetic (seeded Gaussian-blob cube with power-law spectra)",
         "config": {"workload": w.name, "form": args.form, "ny": w.ny, "nx": w.nx, "channels": w.L,
                    "facets": [w.qy, w.qx], "overlap_px": w.overlap, "subcubes": w.C, "levels": w.levels,
                    "bases": "db1-db8+dirac", "weights": args.weights, "duals": "zero at the first step",
+                   "precision": args.precision,
                    "parallelism": "single GPU"},
         "roofline": {"kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": frac, "traffic": traffic,
                      "bytes_per_launch": kb / per_step, "avg_launch_ms": kms / max(launches, 1)},
         "rel_err": rel,
+        "kappa_hist": kappa_hist,
         "tuning": plan.tuning,
         "step_hbm": {"algorithmic_bytes": sb, "achieved_GBs": sb / (ms / 1e3) / 1e9,
                      "frac": sb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},

@@ -68,6 +68,17 @@ extern "C" {
 
 typedef struct fhs_plan fhs_plan;   /* opaque; immutable geometry after creation */
 
+/* Precision forms (fhs_config.precision). */
+#define FHS_PRECISION_FP32 0   /* FP32 storage; wavelet filters, Gram and reconstruction
+                                  accumulated in FP64 (every output within 1e-5 of FP64)  */
+#define FHS_PRECISION_MIXED 1  /* the l21 update's wavelet filters accumulated in FP32; the
+                                  facet Gram of BF16-rounded Z on BF16 MFMA with FP32
+                                  accumulation; eigendecomposition, sigma scaling and the
+                                  reconstruction in FP64 as above.  The weights
+                                  (fhs_reweight) and the synthesis are not affected.  Error
+                                  (vs FP64): W+ about 1e-5, P+ growing as 2^-8 kappa^2 with
+                                  kappa = sigma_1 / min_j t_j of the facet               */
+
 typedef struct {
   int32_t ny, nx;        /* image size, N = ny * nx                                  */
   int32_t nchan;         /* L, channels of the cube                                  */
@@ -76,6 +87,7 @@ typedef struct {
   int32_t overlap_y;     /* low-rankness overlap in pixels toward the top (Sec. 2.4.2) */
   int32_t overlap_x;     /* ... toward the left                                      */
   int32_t levels;        /* wavelet decomposition levels (1..6; 4 in the paper)      */
+  int32_t precision;     /* FHS_PRECISION_FP32 (0) or FHS_PRECISION_MIXED (1)         */
 } fhs_config;
 
 typedef struct {
@@ -147,6 +159,8 @@ typedef struct {
   int32_t ana_direct;      /* bit j set: the analysis of level j+1 loads taps, W and theta straight
                               into registers (no LDS); bit mask over the levels */
   int32_t fin_waves;       /* wavefronts per level-1 synthesis workgroup (4, 6 or 8) */
+  int32_t ana_order;       /* bit j set: the analysis of level j+1 launches the 8 bases of a tile
+                              back to back (tile-major), else basis-major; bit mask over the levels */
 } fhs_tuning;
 
 /* Current launch shapes (defaults after fhs_plan_create). HOST pointer. */

@@ -20,7 +20,7 @@ class FhsError(RuntimeError):
 
 class _Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("ny", "nx", "nchan", "qy", "qx", "n_sub", "overlap_y", "overlap_x", "levels")]
+                ("ny", "nx", "nchan", "qy", "qx", "n_sub", "overlap_y", "overlap_x", "levels", "precision")]
 
 
 class _Sizes(ctypes.Structure):
@@ -32,7 +32,7 @@ class _Sizes(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("ana_rows", ctypes.c_int32 * 6)] + [(n, ctypes.c_int32) for n in
                 ("ana_phase", "syn_rows", "fin_rows", "nuc_seg", "nuc_chunk_rows", "concurrent", "ana_direct",
-                 "fin_waves")]
+                 "fin_waves", "ana_order")]
 
 
 class _PdfbState(ctypes.Structure):
@@ -165,9 +165,10 @@ def _stream(t):
 class Plan:
     """Geometry of one problem (include/fhs.h, fhs_plan_create) plus its workspace."""
 
-    def __init__(self, ny, nx, nchan, qy=1, qx=1, n_sub=1, overlap_y=0, overlap_x=0, levels=4):
+    def __init__(self, ny, nx, nchan, qy=1, qx=1, n_sub=1, overlap_y=0, overlap_x=0, levels=4, precision=0):
+        """precision: 0 = FHS_PRECISION_FP32, 1 = FHS_PRECISION_MIXED (include/fhs.h)."""
         self._lib = lib()
-        self.cfg = _Config(ny, nx, nchan, qy, qx, n_sub, overlap_y, overlap_x, levels)
+        self.cfg = _Config(ny, nx, nchan, qy, qx, n_sub, overlap_y, overlap_x, levels, precision)
         handle = ctypes.c_void_p()
         _check(self._lib.fhs_plan_create(ctypes.byref(self.cfg), ctypes.byref(handle)))
         self._p = handle
@@ -178,6 +179,7 @@ class Plan:
         self.Lc = nchan // n_sub
         self.Q = qy * qx
         self.levels = levels
+        self.precision = precision
         self.workspace = None
 
     def __del__(self):

@@ -102,6 +102,8 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     a.tkx1 = tkx1;
     a.tky = p->tune.ana_rows[j];
     a.direct = (p->tune.ana_direct >> j) & 1;
+    a.tile_major = (p->tune.ana_order >> j) & 1;
+    a.f32 = (mode == 1 && p->cfg.precision == FHS_PRECISION_MIXED) ? 1 : 0;
     a.mode = mode;
     a.active = active;
     // staged row: [sub-cube][column][lane slot], columns of the widest filter
@@ -347,6 +349,7 @@ int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *t
   a.seg = p->tune.nuc_seg;
   a.lc16 = p->lc16;
   a.mode = mode;
+  a.bf16 = (mode == 0 && p->cfg.precision == FHS_PRECISION_MIXED) ? 1 : 0;
   a.q0 = q >= 0 ? q : 0;
   a.eig_q = q;
   a.active = active;

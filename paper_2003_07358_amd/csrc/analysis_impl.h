@@ -28,14 +28,17 @@
 // a fixed four per emitted row, so that the wait at a phase boundary can leave
 // the previous phase's stores in flight.
 //
-// Launch order: basis-major (every tile of the first basis, then of the
-// second, ...).  Orders that place the 8 bases of a tile on one XCD (so that
-// its L2 serves the shared input rows) are kept behind FHS_ANA_XCD; they
-// measured no faster.
+// Launch order (a tuned launch parameter): workgroups are dealt to the 8 XCDs
+// in turn, so each XCD walks its own run of consecutive tiles (horizontal and
+// vertical neighbours share halo rows and columns through that XCD's L2).
+// Basis-major: every tile of db8, then of db7, ... (the heaviest bases first,
+// the light ones fill the tail).  Tile-major: the 8 bases of a tile back to
+// back on one XCD, so that they read its input rows while they are in L2.
 //
 // Arithmetic: FP32 in / FP32 out, FP64 accumulation (detail coefficients are
 // differences of large neighbouring values), unnormalised filters with the
-// 1/3 applied to each emitted coefficient.
+// 1/3 applied to each emitted coefficient.  The mixed-precision form of the
+// l21 update accumulates in FP32 instead (accumulator type T).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -73,18 +76,18 @@ __device__ __forceinline__ float shrink(float u, float thr_th) {
 // v_m and hi = sum_m g[m] v_m, g[m] = (-1)^m h[NTAP-1-m], where v_m = tap(m)
 // is the input at column 2k+1-m.  The high-pass sign stays off the constants
 // (even and odd terms are summed apart), so only the NTAP values h[m] are live.
-template <int NTAP, typename F>
-__device__ __forceinline__ void hfilt(F &&tap, double &lo, double &hi) {
-  using T = Taps<NTAP>;
-  double sl = 0.0, se = 0.0, so = 0.0;
+template <int NTAP, typename T, typename F>
+__device__ __forceinline__ void hfilt(F &&tap, T &lo, T &hi) {
+  using TP = Taps<NTAP>;
+  T sl = 0, se = 0, so = 0;
 #pragma unroll
   for (int m = 0; m < NTAP; ++m) {
-    const double v = static_cast<double>(tap(m));
-    sl = fma(T::hd[m], v, sl);
+    const T v = static_cast<T>(tap(m));
+    sl = fma(static_cast<T>(TP::hd[m]), v, sl);
     if (m & 1)
-      so = fma(T::hd[NTAP - 1 - m], v, so);
+      so = fma(static_cast<T>(TP::hd[NTAP - 1 - m]), v, so);
     else
-      se = fma(T::hd[NTAP - 1 - m], v, se);
+      se = fma(static_cast<T>(TP::hd[NTAP - 1 - m]), v, se);
   }
   lo = sl;
   hi = se - so;
@@ -92,21 +95,21 @@ __device__ __forceinline__ void hfilt(F &&tap, double &lo, double &hi) {
 
 // Vertical filters over the ring (ra(m), rb(m): the low and high horizontal
 // outputs of the row that tap m multiplies): ll, lh through h, hl, hh through g.
-template <int NTAP, typename FA, typename FB>
-__device__ __forceinline__ void vfilt(FA &&ra, FB &&rb, double &ll, double &lh, double &hl, double &hh) {
-  using T = Taps<NTAP>;
-  double sll = 0.0, slh = 0.0, ae = 0.0, ao = 0.0, be = 0.0, bo = 0.0;
+template <int NTAP, typename T, typename FA, typename FB>
+__device__ __forceinline__ void vfilt(FA &&ra, FB &&rb, T &ll, T &lh, T &hl, T &hh) {
+  using TP = Taps<NTAP>;
+  T sll = 0, slh = 0, ae = 0, ao = 0, be = 0, bo = 0;
 #pragma unroll
   for (int m = 0; m < NTAP; ++m) {
-    const double a = ra(m), b = rb(m);
-    sll = fma(T::hd[m], a, sll);
-    slh = fma(T::hd[m], b, slh);
+    const T a = ra(m), b = rb(m);
+    sll = fma(static_cast<T>(TP::hd[m]), a, sll);
+    slh = fma(static_cast<T>(TP::hd[m]), b, slh);
     if (m & 1) {
-      ao = fma(T::hd[NTAP - 1 - m], a, ao);
-      bo = fma(T::hd[NTAP - 1 - m], b, bo);
+      ao = fma(static_cast<T>(TP::hd[NTAP - 1 - m]), a, ao);
+      bo = fma(static_cast<T>(TP::hd[NTAP - 1 - m]), b, bo);
     } else {
-      ae = fma(T::hd[NTAP - 1 - m], a, ae);
-      be = fma(T::hd[NTAP - 1 - m], b, be);
+      ae = fma(static_cast<T>(TP::hd[NTAP - 1 - m]), a, ae);
+      be = fma(static_cast<T>(TP::hd[NTAP - 1 - m]), b, be);
     }
   }
   ll = sll;
@@ -147,10 +150,6 @@ __device__ __forceinline__ void unroll_steps(F &&f) {
   Unroll<0, N>::run(f);
 }
 
-#ifndef FHS_ANA_ROTATE
-#define FHS_ANA_ROTATE 1  // 1: ring slots rotate with the step (loop unrolled over NTAP/2 steps)
-#endif
-
 // Workgroup barrier without a memory fence (the copies are waited for by
 // count before it; LDS accesses are not moved across it).
 __device__ __forceinline__ void barrier() {
@@ -173,7 +172,7 @@ __device__ __forceinline__ void wait_vm_but(int n) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
-template <int NTAP, int MODE, int LCP>
+template <int NTAP, int MODE, int LCP, typename T>
 __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int tile, float *smem) {
   constexpr int H = NTAP / 2;
   if (tile >= B.strips * B.yblocks) return;
@@ -308,9 +307,9 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
   // ring of horizontal outputs: slot i % NTAP holds input row i (relative to
   // the first needed row); the loop below is unrolled over H steps, so that
   // every slot index is a compile-time constant and no entry moves
-  double rl[NTAP], rh[NTAP];
+  T rl[NTAP], rh[NTAP];
 #pragma unroll
-  for (int m = 0; m < NTAP; ++m) rl[m] = rh[m] = 0.0;
+  for (int m = 0; m < NTAP; ++m) rl[m] = rh[m] = 0;
   // LDS word of tap NTAP-1 (the lowest column) of this lane in a staged row
   const int lb = (c * NCP + 2 * kq) * LCP + lane;
   const int tl = c * TKX + kq;  // lane's word in a theta segment
@@ -338,17 +337,18 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       const float *rp = buf + (2 * k + r) * ROW + lb;
-      hfilt<NTAP>([&](int m) { return rp[(NTAP - 1 - m) * LCP]; }, rl[2 * s + r], rh[2 * s + r]);
+      hfilt<NTAP, T>([&](int m) { return rp[(NTAP - 1 - m) * LCP]; }, rl[2 * s + r], rh[2 * s + r]);
     }
     if (g >= H - 1) {
       // tap m multiplies input row 2g+1-m, slot (2s+1-m) mod NTAP
-      double ll, lh, hl, hh;
-      vfilt<NTAP>([&](int m) { return rl[(2 * s + 1 - m + NTAP) % NTAP]; },
+      T ll, lh, hl, hh;
+      vfilt<NTAP, T>([&](int m) { return rl[(2 * s + 1 - m + NTAP) % NTAP]; },
                   [&](int m) { return rh[(2 * s + 1 - m + NTAP) % NTAP]; }, ll, lh, hl, hh);
       const int ky = ky0 + g - (H - 1);
       const uint64_t rb = static_cast<uint64_t>(ky) * band_row;
-      const float vb[4] = {static_cast<float>(lh * kThird), static_cast<float>(hl * kThird),
-                           static_cast<float>(hh * kThird), static_cast<float>(ll * kThird)};
+      const T third = static_cast<T>(kThird);
+      const float vb[4] = {static_cast<float>(lh * third), static_cast<float>(hl * third),
+                           static_cast<float>(hh * third), static_cast<float>(ll * third)};
       const float *wsg = buf + A.lds_wv + 4 * k * kAnaLaneSeg + wl;
       const float *tsg = buf + A.lds_th + 4 * k * kAnaThSeg + tl;
       // exactly four stores per emitted row (the phase wait counts them)
@@ -382,7 +382,6 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
       ++ph;
     }
   };
-#if FHS_ANA_ROTATE
   // one copy of the phase code, H copies of the step body (one per ring
   // rotation, selected by g mod H)
   for (int g = 0, s = 0; g < nsteps; ++g) {
@@ -392,17 +391,6 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
     });
     s = s + 1 == H ? 0 : s + 1;
   }
-#else
-  for (int g = 0; g < nsteps; ++g) {
-    phase_top();
-#pragma unroll
-    for (int m = 0; m + 2 < NTAP; ++m) {
-      rl[m] = rl[m + 2];
-      rh[m] = rh[m + 2];
-    }
-    step(std::integral_constant<int, H - 1>{}, g);
-  }
-#endif
   drain_loads();  // no LDS copy may land after the workgroup ends
 }
 
@@ -412,7 +400,7 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
 // read as zero).  No barriers; the compiler's wait counts track each load, so
 // stores never stall a step.
 
-template <int NTAP, int MODE, int LCP>
+template <int NTAP, int MODE, int LCP, typename T>
 __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B, int tile) {
   constexpr int H = NTAP / 2;
   if (tile >= B.strips * B.yblocks) return;
@@ -476,9 +464,9 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
     }
   };
 
-  double rl[NTAP], rh[NTAP];
+  T rl[NTAP], rh[NTAP];
 #pragma unroll
-  for (int m = 0; m < NTAP; ++m) rl[m] = rh[m] = 0.0;
+  for (int m = 0; m < NTAP; ++m) rl[m] = rh[m] = 0;
   float ta[2][NTAP], tb[2][NTAP];
   float wa[4], tha[4], wb[4], thb[4];
   load_rows(0, ta);
@@ -492,14 +480,15 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
       rh[m] = rh[m + 2];
     }
 #pragma unroll
-    for (int r = 0; r < 2; ++r) hfilt<NTAP>([&](int m) { return t[r][m]; }, rl[NTAP - 2 + r], rh[NTAP - 2 + r]);
+    for (int r = 0; r < 2; ++r) hfilt<NTAP, T>([&](int m) { return t[r][m]; }, rl[NTAP - 2 + r], rh[NTAP - 2 + r]);
     if (g >= H - 1) {
-      double ll, lh, hl, hh;
-      vfilt<NTAP>([&](int m) { return rl[NTAP - 1 - m]; }, [&](int m) { return rh[NTAP - 1 - m]; }, ll, lh, hl,
-                  hh);
+      T ll, lh, hl, hh;
+      vfilt<NTAP, T>([&](int m) { return rl[NTAP - 1 - m]; }, [&](int m) { return rh[NTAP - 1 - m]; }, ll, lh, hl,
+                     hh);
       const int ky = ky0 + g - (H - 1);
-      const float vb[4] = {static_cast<float>(lh * kThird), static_cast<float>(hl * kThird),
-                           static_cast<float>(hh * kThird), static_cast<float>(ll * kThird)};
+      const T third = static_cast<T>(kThird);
+      const float vb[4] = {static_cast<float>(lh * third), static_cast<float>(hl * third),
+                           static_cast<float>(hh * third), static_cast<float>(ll * third)};
 #pragma unroll
       for (int sb = 0; sb < 4; ++sb) {
         if (sb == 3 && !last) continue;
@@ -608,34 +597,32 @@ __global__ void __launch_bounds__(kDiracThreads) dirac_kernel(AnaArgs A) {
 
 // FIRST: level 1 (reads the cube); a separate instantiation so that its
 // launches are profiled on their own.
-template <bool FIRST, int MODE, int LCP, bool DIRECT>
+template <bool FIRST, int MODE, int LCP, bool DIRECT, typename T>
 __device__ __forceinline__ void kernel_body(const AnaArgs &A, float *smem) {
   const int id = blockIdx.x;
   if (id < A.nbase_wg) {
-#ifndef FHS_ANA_XCD
-#define FHS_ANA_XCD 0
-#endif
-#if FHS_ANA_XCD == 1
-    // tile t runs on XCD t % 8, its 8 bases in consecutive workgroups there
-    const int x = id & 7, k = id >> 3;
-    const int b = k & 7, tile = (k >> 3) * 8 + x;
-#elif FHS_ANA_XCD == 2
-    const int x = id & 7, k = id >> 3;
-    const int b = k & 7, tile = x * A.tiles_per_xcd + (k >> 3);
-#else
-    const int b = id / (8 * A.tiles_per_xcd), tile = id - b * 8 * A.tiles_per_xcd;
-#endif
+    int b, tile;
+    if (A.tile_major) {
+      // XCD x = id mod 8 takes its k-th workgroup: the 8 bases of its tile k / 8
+      const int x = id & 7, k = id >> 3;
+      b = 7 - (k & 7);
+      tile = x * A.tiles_per_xcd + (k >> 3);
+    } else {
+      const int per_basis = 8 * A.tiles_per_xcd, r = id - (id / per_basis) * per_basis;
+      b = 7 - id / per_basis;
+      tile = (r & 7) * A.tiles_per_xcd + (r >> 3);
+    }
     // static band indices, each band descriptor read into its own copy (a
     // dynamically indexed descriptor would be copied to scratch)
     switch (b) {
-      case 0: { const AnaBand B = A.b[0]; if (DIRECT) basis_direct<2, MODE, LCP>(A, B, tile); else basis<2, MODE, LCP>(A, B, tile, smem); } break;
-      case 1: { const AnaBand B = A.b[1]; if (DIRECT) basis_direct<4, MODE, LCP>(A, B, tile); else basis<4, MODE, LCP>(A, B, tile, smem); } break;
-      case 2: { const AnaBand B = A.b[2]; if (DIRECT) basis_direct<6, MODE, LCP>(A, B, tile); else basis<6, MODE, LCP>(A, B, tile, smem); } break;
-      case 3: { const AnaBand B = A.b[3]; if (DIRECT) basis_direct<8, MODE, LCP>(A, B, tile); else basis<8, MODE, LCP>(A, B, tile, smem); } break;
-      case 4: { const AnaBand B = A.b[4]; if (DIRECT) basis_direct<10, MODE, LCP>(A, B, tile); else basis<10, MODE, LCP>(A, B, tile, smem); } break;
-      case 5: { const AnaBand B = A.b[5]; if (DIRECT) basis_direct<12, MODE, LCP>(A, B, tile); else basis<12, MODE, LCP>(A, B, tile, smem); } break;
-      case 6: { const AnaBand B = A.b[6]; if (DIRECT) basis_direct<14, MODE, LCP>(A, B, tile); else basis<14, MODE, LCP>(A, B, tile, smem); } break;
-      default: { const AnaBand B = A.b[7]; if (DIRECT) basis_direct<16, MODE, LCP>(A, B, tile); else basis<16, MODE, LCP>(A, B, tile, smem); } break;
+      case 0: { const AnaBand B = A.b[0]; if (DIRECT) basis_direct<2, MODE, LCP, T>(A, B, tile); else basis<2, MODE, LCP, T>(A, B, tile, smem); } break;
+      case 1: { const AnaBand B = A.b[1]; if (DIRECT) basis_direct<4, MODE, LCP, T>(A, B, tile); else basis<4, MODE, LCP, T>(A, B, tile, smem); } break;
+      case 2: { const AnaBand B = A.b[2]; if (DIRECT) basis_direct<6, MODE, LCP, T>(A, B, tile); else basis<6, MODE, LCP, T>(A, B, tile, smem); } break;
+      case 3: { const AnaBand B = A.b[3]; if (DIRECT) basis_direct<8, MODE, LCP, T>(A, B, tile); else basis<8, MODE, LCP, T>(A, B, tile, smem); } break;
+      case 4: { const AnaBand B = A.b[4]; if (DIRECT) basis_direct<10, MODE, LCP, T>(A, B, tile); else basis<10, MODE, LCP, T>(A, B, tile, smem); } break;
+      case 5: { const AnaBand B = A.b[5]; if (DIRECT) basis_direct<12, MODE, LCP, T>(A, B, tile); else basis<12, MODE, LCP, T>(A, B, tile, smem); } break;
+      case 6: { const AnaBand B = A.b[6]; if (DIRECT) basis_direct<14, MODE, LCP, T>(A, B, tile); else basis<14, MODE, LCP, T>(A, B, tile, smem); } break;
+      default: { const AnaBand B = A.b[7]; if (DIRECT) basis_direct<16, MODE, LCP, T>(A, B, tile); else basis<16, MODE, LCP, T>(A, B, tile, smem); } break;
     }
   }
 }
@@ -643,20 +630,21 @@ __device__ __forceinline__ void kernel_body(const AnaArgs &A, float *smem) {
 #ifndef FHS_ANA_WAVES_PER_EU
 #define FHS_ANA_WAVES_PER_EU 4  // register budget of the staged kernel: 128 VGPRs (two 512-thread workgroups per CU)
 #endif
-template <bool FIRST, int MODE, int LCP>
+// (T: FP64 accumulation, or FP32 in the mixed-precision form)
+template <bool FIRST, int MODE, int LCP, typename T>
 __global__ void __launch_bounds__(FHS_ANA_THREADS) __attribute__((amdgpu_waves_per_eu(FHS_ANA_WAVES_PER_EU)))
 kernel(AnaArgs A) {
   extern __shared__ float smem[];
-  kernel_body<FIRST, MODE, LCP, false>(A, smem);
+  kernel_body<FIRST, MODE, LCP, false, T>(A, smem);
 }
 
 // the LDS-free variant keeps its taps in registers (no waves-per-SIMD target)
-template <bool FIRST, int MODE, int LCP>
+template <bool FIRST, int MODE, int LCP, typename T>
 __global__ void __launch_bounds__(FHS_ANA_THREADS) kernel_direct(AnaArgs A) {
-  kernel_body<FIRST, MODE, LCP, true>(A, nullptr);
+  kernel_body<FIRST, MODE, LCP, true, T>(A, nullptr);
 }
 
-template <int MODE>
+template <int MODE, typename T = double>
 int launch_mode(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(static_cast<unsigned>(a.nbase_wg)), block(nthreads);
@@ -669,14 +657,14 @@ int launch_mode(const AnaArgs &a, int nthreads, bool first, size_t lds, void *st
     if (grid.x == 0) break;                                                                    \
     if (a.direct) {                                                                            \
       if (first)                                                                               \
-        hipLaunchKernelGGL((kernel_direct<true, MODE, LCP>), grid, block, 0, s, a);             \
+        hipLaunchKernelGGL((kernel_direct<true, MODE, LCP, T>), grid, block, 0, s, a);          \
       else                                                                                     \
-        hipLaunchKernelGGL((kernel_direct<false, MODE, LCP>), grid, block, 0, s, a);            \
+        hipLaunchKernelGGL((kernel_direct<false, MODE, LCP, T>), grid, block, 0, s, a);         \
     } else {                                                                                   \
       if (first)                                                                               \
-        hipLaunchKernelGGL((kernel<true, MODE, LCP>), grid, block, lds, s, a);          \
+        hipLaunchKernelGGL((kernel<true, MODE, LCP, T>), grid, block, lds, s, a);               \
       else                                                                                     \
-        hipLaunchKernelGGL((kernel<false, MODE, LCP>), grid, block, lds, s, a);         \
+        hipLaunchKernelGGL((kernel<false, MODE, LCP, T>), grid, block, lds, s, a);              \
     }                                                                                          \
     break;
 #define FHS_ANA_CASE(LCP) FHS_ANA_CASE2(LCP, LCP)

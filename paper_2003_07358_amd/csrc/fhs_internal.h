@@ -71,6 +71,8 @@ struct AnaArgs {
   int direct;                 // 1: taps, W and theta loaded straight into registers (no LDS staging)
   int tiles_per_xcd;          // tiles walked by each XCD
   int nbase_wg;               // 64 * tiles_per_xcd workgroups for the wavelet bases
+  int tile_major;             // launch order: 1 the 8 bases of a tile back to back, 0 basis-major
+  int f32;                    // 1: FP32 accumulation of the filters (mixed-precision form, mode 1)
   const int32_t *active;      // [C] sub-cubes whose W (mode 1) or theta (mode 2) may change; null: all
 };
 
@@ -136,6 +138,7 @@ struct NucArgs {
   int seg;                   // pixels per staged segment
   int lc16;                  // Lc rounded up to 16
   int mode;                  // 0: dual update; 1: weights only
+  int bf16;                  // 1: Gram of BF16-rounded Z on BF16 MFMA, FP32 accumulation (mixed form)
   int q0;                    // first spatial facet of the launch (blockIdx.y offset)
   int eig_q;                 // -1: eig over all C*Q facets; else facets c*Q + eig_q, c < C
   const int32_t *active;     // [C] sub-cubes whose P (mode 0) or theta_bar (mode 1) may change; null: all
@@ -178,6 +181,7 @@ struct SnrArgs {
 int launch_analysis(const AnaArgs &a, int nthreads, bool first, void *stream);
 int launch_analysis_m0(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
 int launch_analysis_m1(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
+int launch_analysis_m1f(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
 int launch_analysis_m2(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
 int launch_synthesis(const SynArgs &a, int nthreads, void *stream);
 int launch_synthesis_final(const SynFinalArgs &a, int nthreads, int group, void *stream);

@@ -19,12 +19,22 @@
 // ramp on the last o pixels of its tile (Sec. 2.4.2).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fhs_internal.h"
 #include "lds_stage.h"
 
 namespace fhs {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));  // four bfloat16 bit patterns
+
+// float -> bfloat16 bits, rounding to nearest even (finite inputs)
+__device__ __forceinline__ short bf16_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return static_cast<short>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
 
 
 struct FacetView {
@@ -126,7 +136,13 @@ constexpr int gram_subcubes() {
 // group and sub-cube the NB 16-channel columns of Z are formed once and feed
 // the NB (NB + 1) / 2 block pairs.  The four waves' partials are summed in LDS
 // in a fixed order at the end.
-template <int NB, int K>
+//
+// BF16 (mixed-precision form): Z is formed in FP32, rounded to bfloat16 and
+// multiplied on v_mfma_f32_16x16x16_bf16 with FP32 accumulation, in groups of
+// 16 rows (lane l holds rows 4 (l / 16) .. + 3 of its channel l mod 16: the
+// same operand serves as A = Z^T and B = Z, as in the FP64 form); the
+// partials are summed across waves in FP64.
+template <int NB, int K, bool BF16>
 __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
   using PR = Pairs<NB>;
   extern __shared__ float sm[];
@@ -143,11 +159,12 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
   const bool with_p = A.p != nullptr;
   const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const int c0 = blockIdx.z * K, nc = min(K, g.C - c0);
-  v4d acc[K][PR::n];
+  using Acc = typename std::conditional<BF16, v4f, v4d>::type;
+  Acc acc[K][PR::n];
 #pragma unroll
   for (int kc = 0; kc < K; ++kc)
 #pragma unroll
-    for (int t = 0; t < PR::n; ++t) acc[kc][t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < PR::n; ++t) acc[kc][t] = Acc{0, 0, 0, 0};
 
   issue_seg(A, F, seg_of(0, y0, nsx, S, F.hx), sm, dsh[0], with_p);
   for (int i = 0; i < nseg; ++i) {
@@ -156,30 +173,61 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
     const float *buf = sm + (i & 1) * BUF;
     const double *d = dsh[i & 1];
     const int n = seg_of(i, y0, nsx, S, F.hx).n;
-    for (int k4 = wave; k4 < S / 4; k4 += 4) {
-      const int r = 4 * k4 + ln / 16;
-      const bool rv = r < n;
-      const double dr = d[r];
+    if constexpr (BF16) {
+      for (int k16 = wave; k16 < S / 16; k16 += 4) {
+        const int rb = 16 * k16 + 4 * (ln / 16);
 #pragma unroll
-      for (int kc = 0; kc < K; ++kc) {
-        if (kc < nc) {
-          // Z[r][ch] = P_c[r][ch] + D_r X[r][c + ch C], ch = 16 b + (ln % 16)
-          const int c = c0 + kc, ch0 = ln & 15;
-          const float *xr = buf + r * L + c + ch0 * g.C;
-          const float *pr = buf + S * L + (c * S + r) * g.Lc + ch0;
-          double z[NB];
+        for (int kc = 0; kc < K; ++kc) {
+          if (kc < nc) {
+            const int c = c0 + kc, ch0 = ln & 15;
+            v4s z[NB];
 #pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            const bool ok = rv && 16 * b + ch0 < g.Lc;
-            const double pv = with_p ? static_cast<double>(pr[16 * b]) : 0.0;
-            z[b] = ok ? fma(dr, static_cast<double>(xr[16 * b * g.C]), pv) : 0.0;
+            for (int b = 0; b < NB; ++b) {
+              const bool chv = 16 * b + ch0 < g.Lc;
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                const int r = rb + t;
+                const bool ok = chv && r < n;
+                const float xv = ok ? buf[r * L + c + (16 * b + ch0) * g.C] : 0.0f;
+                const float pv = (ok && with_p) ? buf[S * L + (c * S + r) * g.Lc + 16 * b + ch0] : 0.0f;
+                z[b][t] = bf16_bits(ok ? fmaf(static_cast<float>(d[r]), xv, pv) : 0.0f);
+              }
+            }
+            int t = 0;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+              for (int bj = bi; bj < NB; ++bj, ++t)
+                acc[kc][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(z[bi], z[bj], acc[kc][t], 0, 0, 0);
           }
-          int t = 0;
+        }
+      }
+    } else {
+      for (int k4 = wave; k4 < S / 4; k4 += 4) {
+        const int r = 4 * k4 + ln / 16;
+        const bool rv = r < n;
+        const double dr = d[r];
 #pragma unroll
-          for (int bi = 0; bi < NB; ++bi)
+        for (int kc = 0; kc < K; ++kc) {
+          if (kc < nc) {
+            // Z[r][ch] = P_c[r][ch] + D_r X[r][c + ch C], ch = 16 b + (ln % 16)
+            const int c = c0 + kc, ch0 = ln & 15;
+            const float *xr = buf + r * L + c + ch0 * g.C;
+            const float *pr = buf + S * L + (c * S + r) * g.Lc + ch0;
+            double z[NB];
 #pragma unroll
-            for (int bj = bi; bj < NB; ++bj, ++t)
-              acc[kc][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(z[bi], z[bj], acc[kc][t], 0, 0, 0);
+            for (int b = 0; b < NB; ++b) {
+              const bool ok = rv && 16 * b + ch0 < g.Lc;
+              const double pv = with_p ? static_cast<double>(pr[16 * b]) : 0.0;
+              z[b] = ok ? fma(dr, static_cast<double>(xr[16 * b * g.C]), pv) : 0.0;
+            }
+            int t = 0;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+              for (int bj = bi; bj < NB; ++bj, ++t)
+                acc[kc][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(z[bi], z[bj], acc[kc][t], 0, 0, 0);
+          }
         }
       }
     }
@@ -197,12 +245,13 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
         for (int bj = bi; bj < NB; ++bj, ++t) {
           __syncthreads();
 #pragma unroll
-          for (int v = 0; v < 4; ++v) red[wave * 256 + v * 64 + ln] = acc[kc][t][v];
+          for (int v = 0; v < 4; ++v) red[wave * 256 + v * 64 + ln] = static_cast<double>(acc[kc][t][v]);
           __syncthreads();
           const int e = threadIdx.x, v = e >> 6, l = e & 63;
           const double sum = red[e] + red[256 + e] + red[512 + e] + red[768 + e];
-          // v_mfma_f64_16x16x4f64 result layout: lane l holds D[4 v + l / 16][l % 16]
-          const int ii = 16 * bi + 4 * v + l / 16, jj = 16 * bj + (l & 15);
+          // result layouts: v_mfma_f64_16x16x4f64 has lane l hold D[4 v + l / 16][l % 16],
+          // v_mfma_f32_16x16x16_bf16 D[4 (l / 16) + v][l % 16]
+          const int ii = 16 * bi + (BF16 ? 4 * (l / 16) + v : 4 * v + l / 16), jj = 16 * bj + (l & 15);
           const int f = (c0 + kc) * Q + q;
           A.gram[(static_cast<int64_t>(f) * A.chunks + chunk) * A.lc16 * A.lc16 + ii * A.lc16 + jj] = sum;
         }
@@ -643,11 +692,18 @@ int launch_nuc_gram(const NucArgs &a, int nspatial, void *stream) {
 #define FHS_GRAM_CASE(NB)                                                                               \
   case NB: {                                                                                            \
     constexpr int KM = gram_subcubes<NB>();                                                             \
-    if (a.g.C == 1 || KM == 1)                                                                          \
-      hipLaunchKernelGGL((nuc_gram_kernel<NB, 1>), dim3(a.chunks, nspatial, a.g.C), dim3(256), lds, s, a); \
-    else                                                                                                \
-      hipLaunchKernelGGL((nuc_gram_kernel<NB, KM>), dim3(a.chunks, nspatial, (a.g.C + KM - 1) / KM),     \
+    if (a.bf16) {                                                                                       \
+      if (a.g.C == 1 || KM == 1)                                                                        \
+        hipLaunchKernelGGL((nuc_gram_kernel<NB, 1, true>), dim3(a.chunks, nspatial, a.g.C), dim3(256), lds, s, a); \
+      else                                                                                              \
+        hipLaunchKernelGGL((nuc_gram_kernel<NB, KM, true>), dim3(a.chunks, nspatial, (a.g.C + KM - 1) / KM), \
+                           dim3(256), lds, s, a);                                                       \
+    } else if (a.g.C == 1 || KM == 1) {                                                                 \
+      hipLaunchKernelGGL((nuc_gram_kernel<NB, 1, false>), dim3(a.chunks, nspatial, a.g.C), dim3(256), lds, s, a); \
+    } else {                                                                                            \
+      hipLaunchKernelGGL((nuc_gram_kernel<NB, KM, false>), dim3(a.chunks, nspatial, (a.g.C + KM - 1) / KM), \
                          dim3(256), lds, s, a);                                                         \
+    }                                                                                                   \
   } break;
   switch (a.lc16 / 16) {
     FHS_GRAM_CASE(1)

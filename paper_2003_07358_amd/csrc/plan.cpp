@@ -78,6 +78,8 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   if (c.nchan / c.n_sub > kMaxLc) return fail(FHS_EUNSUPPORTED, "more than 64 channels per sub-cube");
   if (c.overlap_y < 0 || c.overlap_x < 0) return fail(FHS_EINVAL, "negative overlap");
   if (c.levels < 1 || c.levels > kMaxLevels) return fail(FHS_EINVAL, "levels must be in 1..6");
+  if (c.precision != FHS_PRECISION_FP32 && c.precision != FHS_PRECISION_MIXED)
+    return fail(FHS_EINVAL, "precision must be FHS_PRECISION_FP32 or FHS_PRECISION_MIXED");
   if (static_cast<int64_t>(c.ny) * c.nx * c.nchan > (int64_t(1) << 40)) return fail(FHS_EUNSUPPORTED, "cube too large");
 
   fhs_plan *p = new (std::nothrow) fhs_plan();
@@ -229,6 +231,7 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
     t.nuc_chunk_rows = std::max(1, 4096 / p->max_hx);
     t.concurrent = 1;
     t.ana_direct = 0;
+    t.ana_order = 0;
     p->nuc_chunk_min = std::max(1, t.nuc_chunk_rows / 2);
     p->gram_chunks = (p->max_hy + p->nuc_chunk_min - 1) / p->nuc_chunk_min;
   }
@@ -349,6 +352,8 @@ int fhs_plan_set_tuning(fhs_plan *p, const fhs_tuning *t) {
   if (t->ana_direct < 0 || t->ana_direct >= (1 << kMaxLevels))
     return fail(FHS_EINVAL, "ana_direct must be a bit mask of levels (0 .. 63)");
   if (t->fin_waves != 4 && t->fin_waves != 6 && t->fin_waves != 8) return fail(FHS_EINVAL, "fin_waves must be 4, 6 or 8");
+  if (t->ana_order < 0 || t->ana_order >= (1 << kMaxLevels))
+    return fail(FHS_EINVAL, "ana_order must be a bit mask of levels (0 .. 63)");
   p->tune = *t;
   return FHS_OK;
 }

@@ -24,12 +24,8 @@
 #include "fhs_internal.h"
 #include "lds_stage.h"
 
-#ifndef FHS_FINAL_SPLIT
-#define FHS_FINAL_SPLIT 4
-#endif
-#ifndef FHS_FINAL_WPE
-#define FHS_FINAL_WPE 2
-#endif
+// waves per SIMD targeted by a level-1 synthesis group of more than two bases
+constexpr int kFinalWavesPerEU = 2;
 
 namespace fhs {
 
@@ -274,7 +270,7 @@ int launch_synthesis(const SynArgs &a, int nthreads, void *stream) {
 namespace {
 
 // Bases [0, kFinalSplit) go in the first final-level pass, the rest in the second.
-constexpr int kFinalSplit = FHS_FINAL_SPLIT;
+constexpr int kFinalSplit = 4;
 
 // LDS floats of one staged band row of basis b.
 __device__ __forceinline__ int fin_segp(int tk, int b, int L) { return round_up((tk + b) * L, 64); }
@@ -321,7 +317,7 @@ struct RingSet<BEND, BEND, P> {
 // flight, and the barrier carries no memory fence.
 template <int B0, int B1, bool FIRST, int P>
 __global__ void __launch_bounds__(FHS_SYN_THREADS)
-__attribute__((amdgpu_waves_per_eu(B1 - B0 <= 2 ? 2 * FHS_FINAL_WPE : FHS_FINAL_WPE)))
+__attribute__((amdgpu_waves_per_eu(B1 - B0 <= 2 ? 2 * kFinalWavesPerEU : kFinalWavesPerEU)))
 syn_final_kernel(SynFinalArgs A) {
   extern __shared__ float smem[];
   const int L = A.L, Lcp = A.Lcp, C = A.C, Lc = A.Lc;

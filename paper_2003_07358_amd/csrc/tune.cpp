@@ -99,6 +99,11 @@ extern "C" int fhs_plan_autotune(fhs_plan *p, const float *xcheck, float *pdual,
         c.ana_direct = (best.ana_direct & ~(1 << j)) | (d << j);
         trial(c);
       }
+      for (int o : {0, 1}) {
+        fhs_tuning c = best;
+        c.ana_order = (best.ana_order & ~(1 << j)) | (o << j);
+        trial(c);
+      }
       for (int rows : {8, 16, 32, 64, 128}) {
         fhs_tuning c = best;
         c.ana_rows[j] = rows;

@@ -9,6 +9,11 @@
         (FETCH_SIZE, WRITE_SIZE), each scaled by the reading of a reference
         copy kernel that moves a known number of bytes
 
+    python -m paper_2003_07358_amd.profiling counters DIR [DIR ...] --kernel REGEX [--kernel REGEX ...]
+            --out FILE --command CMD
+        per-dispatch averages of every counter of one or more --pmc runs for
+        the kernels matching each REGEX
+
 DIR is the rocprofv3 output directory (its SQLite results database).  The
 source hash written with the traffic summary names the kernel sources the
 counters were taken on; a summary taken on other sources is stale.
@@ -144,6 +149,24 @@ def cmd_traffic(a):
     print(json.dumps(res, indent=1))
 
 
+def cmd_counters(a):
+    res = {"command": a.command, "kernels": {}}
+    for pattern in a.kernel:
+        entry = {}
+        for d in a.dirs:
+            c = _db(d)
+            names = [r[0] for r in c.execute("select distinct counter_name from counters_collection").fetchall()]
+            for cn in names:
+                vals = _matching(counter_per_dispatch(d, cn), pattern)
+                entry[cn] = sum(vals) / len(vals)
+                entry[cn + "_dispatches"] = len(vals)
+        res["kernels"][pattern] = entry
+    with open(a.out, "w") as fh:
+        json.dump(res, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(res, indent=1))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -162,8 +185,13 @@ def main(argv=None):
     t.add_argument("--out", required=True)
     t.add_argument("--command", default="")
     t.add_argument("--sources", default="", help="kernel whose source list the hash covers (default: all)")
+    k = sub.add_parser("counters")
+    k.add_argument("dirs", nargs="+")
+    k.add_argument("--kernel", action="append", required=True)
+    k.add_argument("--out", required=True)
+    k.add_argument("--command", default="")
     a = ap.parse_args(argv)
-    (cmd_stats if a.cmd == "stats" else cmd_traffic)(a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -121,7 +121,8 @@ def test_tuning_roundtrip_and_validation():
     t2 = plan.tuning
     assert t2["ana_rows"][:4] == [32, 64, 128, 16] and t2["fin_rows"] == 256 and t2["nuc_seg"] == 16
     for bad in ({"ana_rows": [12, 64, 64, 64, 64, 64]}, {"ana_phase": 3}, {"syn_rows": 20}, {"nuc_seg": 48},
-                {"nuc_chunk_rows": 0}, {"concurrent": 2}, {"ana_direct": 64}, {"fin_waves": 5}):
+                {"nuc_chunk_rows": 0}, {"concurrent": 2}, {"ana_direct": 64}, {"fin_waves": 5},
+                {"ana_order": 64}):
         with pytest.raises(fhs.FhsError):
             plan.tuning = bad
     assert plan.tuning == t2   # a rejected setting leaves the plan unchanged

@@ -328,12 +328,14 @@ def test_per_facet_form_matches_batched(name):
                                   "tiny_7x9x3_levels2"])
 def test_direct_analysis_matches_staged(name):
     """The LDS-free analysis (taps, W and theta loaded into registers) gives the
-    same coefficients, bit for bit, as the LDS-staged one, for every mode."""
+    same coefficients, bit for bit, as the LDS-staged one, for every mode; so
+    does either launch order (basis-major or tile-major)."""
     pb, plan = make(name, warm=True)
     x = dev(pb.X)
     outs = []
-    for direct in (0, 63, 0b0101):     # staged, direct at every level, mixed
-        plan.tuning = {"ana_direct": direct}
+    # staged, direct at every level, mixed; tile-major order at every level and mixed
+    for direct, order in ((0, 0), (63, 0), (0b0101, 0), (0, 63), (0b0110, 0b0011)):
+        plan.tuning = {"ana_direct": direct, "ana_order": order}
         w0 = torch.empty(plan.sizes["n_w"], dtype=torch.float32, device="cuda")
         plan.sara_analysis(x, w0)
         w1, g1 = dev(pb.W_flat()), torch.empty(plan.sizes["n_x"], device="cuda")
