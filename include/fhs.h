@@ -386,6 +386,15 @@ int fhs_reweighting_solve(const fhs_plan *plan, const fhs_pdfb_state *state, con
 
 /* ---------------------------------------------------------------- diagnostics */
 
+/* Counters kept in the plan's workspace since it was attached (or last
+ * reset): out[0] = nuclear eigendecompositions whose cyclic Jacobi still had
+ * off-diagonal energy above 1e-20 of the total after its 40 sweeps (not
+ * converged; the step went on with the last rotation), out[1] = facets whose
+ * Gram matrix was not finite (NaN or Inf in the input).  HOST out; reads them
+ * on `stream` and synchronises it; reset != 0 clears them afterwards.  Not a
+ * compute call (do not capture it in a graph). */
+int fhs_plan_diagnostics(const fhs_plan *plan, int64_t out[2], int32_t reset, void *stream);
+
 /* Kernel identifiers for fhs_plan_profile. */
 #define FHS_K_ANALYSIS_L1 0   /* analysis, level 1 of all bases + Dirac (fused l21 update) */
 #define FHS_K_ANALYSIS 1      /* analysis, levels >= 2                                    */

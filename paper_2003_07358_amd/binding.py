@@ -105,6 +105,8 @@ SYMBOLS = {
     "fhs_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fhs_graph_destroy": (None, [ctypes.c_void_p]),
     "fhs_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "fhs_plan_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                            ctypes.c_void_p]),
     "fhs_plan_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -439,6 +441,16 @@ class Plan:
         """Time every launch of `kernel` (name from KERNELS, or None to stop)."""
         kid = -1 if kernel is None else KERNELS[kernel]
         _check(self._lib.fhs_plan_profile(self._p, kid, max_launches))
+
+    def diagnostics(self, reset=False):
+        """dict(eig_not_converged, gram_not_finite): counters since the
+        workspace was attached or last reset (synchronises the stream)."""
+        import torch
+        self._need_ws()
+        out = (ctypes.c_int64 * 2)()
+        _check(self._lib.fhs_plan_diagnostics(self._p, out, int(bool(reset)),
+                                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        return {"eig_not_converged": out[0], "gram_not_finite": out[1]}
 
     def profile_read(self):
         """(total ms, launches) since the last read."""

@@ -349,6 +349,7 @@ int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *t
   a.seg = p->tune.nuc_seg;
   a.lc16 = p->lc16;
   a.mode = mode;
+  a.diag = reinterpret_cast<unsigned *>(static_cast<char *>(ws_base(p)) + p->ws_diag);
   a.bf16 = (mode == 0 && p->cfg.precision == FHS_PRECISION_MIXED) ? 1 : 0;
   a.q0 = q >= 0 ? q : 0;
   a.eig_q = q;
@@ -517,6 +518,21 @@ int fhs_reweight(const fhs_plan *p, const float *x, const double *upsilon, const
   if (int rc = check_plan(p)) return rc;
   if (!x || !upsilon || !upsilon_bar || !theta || !theta_bar) return fail(FHS_EINVAL, "fhs_reweight: null array");
   return reweight(p, x, upsilon, upsilon_bar, theta, theta_bar, stream, nullptr);
+}
+
+int fhs_plan_diagnostics(const fhs_plan *p, int64_t out[2], int32_t reset, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!out) return fail(FHS_EINVAL, "fhs_plan_diagnostics: null output");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned h[2] = {0, 0};
+  void *d = static_cast<char *>(p->ws) + p->ws_diag;
+  if (hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return fail(FHS_EHIP, "fhs_plan_diagnostics: reading the counters failed");
+  out[0] = h[0];
+  out[1] = h[1];
+  if (reset && (hipMemsetAsync(d, 0, sizeof(h), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess))
+    return fail(FHS_EHIP, "fhs_plan_diagnostics: clearing the counters failed");
+  return FHS_OK;
 }
 
 }  // extern "C"

@@ -142,6 +142,7 @@ struct NucArgs {
   int q0;                    // first spatial facet of the launch (blockIdx.y offset)
   int eig_q;                 // -1: eig over all C*Q facets; else facets c*Q + eig_q, c < C
   const int32_t *active;     // [C] sub-cubes whose P (mode 0) or theta_bar (mode 1) may change; null: all
+  unsigned *diag;            // [2] counters: eigendecompositions not converged, non-finite Grams (or null)
 };
 
 struct GatherArgs {
@@ -232,7 +233,8 @@ struct fhs_plan {
   int ntap[fhs::kBases];
   // workspace layout (bytes)
   int64_t ws_ll[fhs::kBases][fhs::kMaxLevels];
-  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_red = 0, ws_factor = 0, ws_ctl = 0, ws_active = 0, ws_bytes = 0;
+  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_red = 0, ws_factor = 0, ws_ctl = 0, ws_active = 0, ws_diag = 0;
+  int64_t ws_bytes = 0;
   int64_t red_ppb = 0;                     // closure: pixels per block
   int red_blocks = 0;                      // closure: blocks
   int gram_chunks = 0, max_rows = 0;       // Gram partial slots per facet (workspace capacity)

@@ -281,14 +281,19 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return s;
 }
 
-__global__ void __launch_bounds__(256) nuc_eig_kernel(NucArgs A) {
+// One workgroup of kEigThreads per facet: each Jacobi round's row and column
+// updates ((n/2) n elements each) spread over all its threads.
+constexpr int kEigThreads = 1024;
+constexpr int kEigSweeps = 40;
+
+__global__ void __launch_bounds__(kEigThreads) nuc_eig_kernel(NucArgs A) {
   __shared__ double Am[kMaxLc][kMaxLc + 1];
   __shared__ double Vm[kMaxLc][kMaxLc + 1];
   __shared__ double cs_c[kMaxLc / 2], cs_s[kMaxLc / 2];
   __shared__ int cs_p[kMaxLc / 2], cs_q[kMaxLc / 2];
   __shared__ double lam[kMaxLc], hv[kMaxLc];
   __shared__ int rank[kMaxLc];
-  __shared__ double red[4];
+  __shared__ double red[kEigThreads / 64];
   const NucGeom &g = A.g;
   const int f = A.eig_q < 0 ? blockIdx.x : blockIdx.x * (g.qy * g.qx) + A.eig_q;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -307,7 +312,7 @@ __global__ void __launch_bounds__(256) nuc_eig_kernel(NucArgs A) {
     Vm[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  for (int sweep = 0; sweep <= kEigSweeps; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int idx = tid; idx < n2 * n2; idx += nth) {
       const int i = idx / n2, j = idx - (idx / n2) * n2;
@@ -317,7 +322,17 @@ __global__ void __launch_bounds__(256) nuc_eig_kernel(NucArgs A) {
     }
     off = block_sum(off, red);
     tot = block_sum(tot, red);
+    // diagnostics: a Gram that is not finite (NaN or Inf in the input), or
+    // off-diagonal energy still above 1e-20 of the total after the last sweep
+    if (!(tot < __builtin_huge_val())) {
+      if (tid == 0 && A.diag != nullptr) atomicAdd(A.diag + 1, 1u);
+      break;
+    }
     if (!(off > 1e-30 * tot)) break;
+    if (sweep == kEigSweeps) {
+      if (tid == 0 && A.diag != nullptr && off > 1e-20 * tot) atomicAdd(A.diag, 1u);
+      break;
+    }
     for (int r = 0; r < n2 - 1; ++r) {
       if (tid < n2 / 2) {
         int p, q;
@@ -717,7 +732,7 @@ int launch_nuc_gram(const NucArgs &a, int nspatial, void *stream) {
 }
 
 int launch_nuc_eig(const NucArgs &a, int nfacets, void *stream) {
-  hipLaunchKernelGGL(nuc_eig_kernel, dim3(nfacets), dim3(256), 0, static_cast<hipStream_t>(stream), a);
+  hipLaunchKernelGGL(nuc_eig_kernel, dim3(nfacets), dim3(kEigThreads), 0, static_cast<hipStream_t>(stream), a);
   return check_launch("nuc_eig");
 }
 

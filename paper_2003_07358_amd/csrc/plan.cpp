@@ -261,6 +261,9 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   // per-sub-cube activity flags of the reweighting solve
   p->ws_active = ws;
   ws = align256(ws + static_cast<int64_t>(p->C) * 4);
+  // diagnostic counters (cleared when the workspace is attached)
+  p->ws_diag = ws;
+  ws = align256(ws + 2 * 4);
   p->ws_bytes = ws;
   *out = p;
   return FHS_OK;
@@ -365,6 +368,9 @@ int fhs_plan_set_workspace(fhs_plan *p, void *dev_ptr, int64_t bytes) {
   if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0) return fail(FHS_EINVAL, "workspace must be 256-byte aligned");
   p->ws = dev_ptr;
   p->ws_given = bytes;
+  if (hipMemset(static_cast<char *>(dev_ptr) + p->ws_diag, 0, 2 * sizeof(unsigned)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess)
+    return fail(FHS_EHIP, "fhs_plan_set_workspace: clearing the diagnostic counters failed");
   if (!p->side) {
     // side stream (default priority) and fork / join events for the
     // concurrent nuclear chain; without them the step runs on one stream

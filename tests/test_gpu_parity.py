@@ -349,3 +349,23 @@ def test_direct_analysis_matches_staged(name):
             log(f"    {nm}: max |direct - staged| = {np.max(np.abs(a - b)):.3e}")
             assert np.array_equal(a, b), nm
     check("W+ (direct)", outs[1][1], np.concatenate(pb.oracle_l21()[0], axis=1).reshape(-1))
+
+
+def test_diagnostics_count_non_finite_facets():
+    """A NaN in one facet's window makes that facet's Gram non-finite: the
+    diagnostic counter names exactly the facets whose windows hold it (the
+    pixel lies in the bottom-right tile only, inside no other window); clean
+    inputs count nothing, and the eigensolver converges on every facet."""
+    pb, plan = make("cfg1_256x256x20_q2x2_o32", warm=True)
+    args = (dev(pb.theta_bar_flat()), dev(pb.mu_bar_flat()), 1.0)
+    g = torch.zeros(plan.sizes["n_x"], device="cuda")
+    plan.diagnostics(reset=True)
+    plan.nuclear_dual_update(dev(pb.X), dev(pb.P_flat()), *args, g, 0.0)
+    assert plan.diagnostics(reset=True) == {"eig_not_converged": 0, "gram_not_finite": 0}
+    X = pb.X.copy()
+    X[250, 250, 3] = np.nan
+    plan.nuclear_dual_update(dev(X), dev(pb.P_flat()), *args, g, 0.0)
+    d = plan.diagnostics(reset=True)
+    log(f"    diagnostics with one NaN pixel: {d}")
+    assert d == {"eig_not_converged": 0, "gram_not_finite": 1}
+    assert plan.diagnostics() == {"eig_not_converged": 0, "gram_not_finite": 0}
