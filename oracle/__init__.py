@@ -20,7 +20,8 @@ against the paper by eye:
                     weighted SVT, l21 row shrink).
 * ``step``       -- one facet step of Algorithm 2: the weighted nuclear-norm
                     dual update, the weighted l21 dual update and the gather
-                    into the primal gradient (facet part of the aggregation).
+                    into the primal gradient (facet part of the aggregation);
+                    its randomized form updates a random subset of facets.
 * ``heuristics`` -- regularisation parameters (eqs. heuristic_fhs_sparsity and
                     heuristic_fhs_low_rank) and reweighting weights
                     (eqs. facet_hypersara_rank and facet_hypersara_sparsity).

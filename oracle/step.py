@@ -21,6 +21,10 @@ The faceted wavelet transform is exactly the global one (Sec. 2.4.2), so the
 l21 update is computed here on the global transform; `sara.faceted_*` provide
 the explicit faceted form that the tests pin against it.
 
+facet_prox_step_select is the randomized form (Sec. 3.2): only a random
+subset of the facets update their duals at an iteration, the draw being an
+input.
+
 Spectral sub-cubes (Sec. 2.4.1) are channel-interleaved: sub-cube c holds the
 channels c, c + C, c + 2C, ... of the cube.
 
@@ -88,3 +92,52 @@ def facet_prox_step(xcheck, P, W, theta, theta_bar, mu, mu_bar, zeta, kappa, geo
     P_new, Gn = nuclear_dual_update(xcheck, P, theta_bar, mu_bar, zeta, geom, C)
     W_new, Gs = l21_dual_update(xcheck, W, theta, mu, kappa, geom.levels, C)
     return P_new, W_new, Gn + Gs
+
+
+def facet_prox_step_select(xcheck, P, W, theta, theta_bar, mu, mu_bar, zeta, kappa, geom, select, C=1):
+    """Randomized form of the facet step (Sec. 3.2, random selection of the
+    facet dual variables updated at an iteration): only the facets (c, q) with
+    select[c][q] true update their duals; the others keep them.  The facet
+    duals of (c, q) are P_{c,q} and the l21 dual W_{c,q}, i.e. the coefficient
+    rows facet q owns in every band (Sec. 2.4.2).  The aggregation sums the
+    contributions of every facet's current duals.
+
+    select: (C, Q) booleans (the random draw is an input).  Returns
+    (P_new, W_new, G) in the layouts of facet_prox_step.
+    """
+    ny, nx, L = xcheck.shape
+    chans = subcube_channels(L, C)
+    levels = geom.levels
+    P_new = []
+    for c in range(C):
+        row = []
+        for q, f in enumerate(geom.facets):
+            if select[c][q]:
+                Lc = len(chans[c])
+                Z = np.asarray(P[c][q], dtype=np.float64).reshape(-1, Lc) + facet_matrix(xcheck, f, chans[c])
+                t = (mu_bar[c][q] / zeta) * np.asarray(theta_bar[c][q], dtype=np.float64)
+                row.append(prox.weighted_svt_complement(Z, t).reshape(f.nuc_shape + (Lc,)))
+            else:
+                row.append(np.array(P[c][q], dtype=np.float64))
+        P_new.append(row)
+    W_new = []
+    for c in range(C):
+        # the update of every row, kept where the owning facet is selected
+        A = sara.flatten(sara.analysis(np.asarray(xcheck, dtype=np.float64)[..., chans[c]], levels))
+        U = np.asarray(W[c], dtype=np.float64) + A
+        upd = sara.unflatten(prox.l21_prox_complement(U, (mu[c] / kappa) * np.asarray(theta[c], dtype=np.float64)),
+                             ny, nx, levels)
+        out = sara.unflatten(np.array(W[c], dtype=np.float64), ny, nx, levels)
+        for q, f in enumerate(geom.facets):
+            if not select[c][q]:
+                continue
+            for k, ((r0, r1), (c0, c1)) in enumerate(geom.owned_rects(f)):
+                out[k][r0:r1, c0:c1] = upd[k][r0:r1, c0:c1]
+        W_new.append(sara.flatten(out))
+    G = np.zeros((ny, nx, L))
+    for c in range(C):
+        for q, f in enumerate(geom.facets):
+            (y0, y1), (x0, x1) = f.nuc_window
+            G[y0:y1, x0:x1][..., chans[c]] += zeta * f.window()[..., None] * P_new[c][q]
+        G[..., chans[c]] += kappa * sara.synthesis(sara.unflatten(W_new[c], ny, nx, levels), ny, nx, levels)
+    return P_new, W_new, G

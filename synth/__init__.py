@@ -166,3 +166,9 @@ def warm_w_scale(mu_c):
 def warm_p_scale(mu_bar_f, n_rows):
     """Amplitude of the warm nuclear dual of a facet with n_rows pixels."""
     return 0.3 * float(mu_bar_f) / np.sqrt(n_rows)
+
+
+def facet_selection(C, Q, prob, seed):
+    """Random draw of the facets whose duals a randomized step updates:
+    (C, Q) booleans, each true with probability prob."""
+    return rng(seed).random((C, Q)) < prob
