@@ -223,6 +223,20 @@ int fhs_facet_prox_step(const fhs_plan *plan, const float *xcheck, float *p_inou
                         const double *mu, const double *mu_bar, double zeta, double kappa,
                         float *grad, void *stream);
 
+/* Randomized form of the step (Sec. 3.2: a random subset of the facet dual
+ * variables is updated at an iteration).  select: device uint8 [C][Q]
+ * (facet descriptor order f = c Q + q), drawn by the caller; nonzero updates
+ * the duals of facet f: P_f, and the l21 rows facet q owns in sub-cube c in
+ * every band (its coefficients of the faceted transform, Sec. 2.4.2; the
+ * Dirac rows of its tile).  The other facets keep their P and W bit for bit.
+ * grad is then the aggregation of every facet's current duals, as in
+ * fhs_facet_prox_step (overwritten).  Other arguments as there; every
+ * selected facet gets the same result as fhs_facet_prox_step gives it. */
+int fhs_facet_prox_step_select(const fhs_plan *plan, const float *xcheck, float *p_inout,
+                               float *w_inout, const float *theta, const double *theta_bar,
+                               const double *mu, const double *mu_bar, double zeta, double kappa,
+                               const uint8_t *select, float *grad, void *stream);
+
 /* The same step in the per-facet execution form (the paper's organisation:
  * one facet at a time, Sec. 2.4 and Fig. 4): every operator is launched once
  * per spatial facet on the coefficients / pixels / window rows that facet

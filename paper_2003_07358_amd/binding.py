@@ -83,6 +83,11 @@ SYMBOLS = {
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_facet_prox_step_select": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_void_p]),
     "fhs_facet_prox_step_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
@@ -323,6 +328,22 @@ class Plan:
             self._t(theta_bar, s["n_theta_bar"], torch.float64, "theta_bar"),
             self._t(mu, self.C, torch.float64, "mu"),
             self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"), float(zeta), float(kappa),
+            self._t(grad, s["n_x"], torch.float32, "grad"), _stream(xcheck)))
+
+    def facet_prox_step_select(self, xcheck, p, w, theta, theta_bar, mu, mu_bar, zeta, kappa, select, grad):
+        """fhs_facet_prox_step_select: the randomized step; select is a device
+        uint8 tensor of n_facets flags (facet descriptor order)."""
+        import torch
+        self._need_ws()
+        s = self.sizes
+        _check(self._lib.fhs_facet_prox_step_select(
+            self._p, self._t(xcheck, s["n_x"], torch.float32, "xcheck"),
+            self._t(p, s["n_p"], torch.float32, "p"), self._t(w, s["n_w"], torch.float32, "w"),
+            self._t(theta, s["n_theta"], torch.float32, "theta"),
+            self._t(theta_bar, s["n_theta_bar"], torch.float64, "theta_bar"),
+            self._t(mu, self.C, torch.float64, "mu"),
+            self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"), float(zeta), float(kappa),
+            self._t(select, s["n_facets"], torch.uint8, "select"),
             self._t(grad, s["n_x"], torch.float32, "grad"), _stream(xcheck)))
 
     def facet_prox_step_noalloc(self, xcheck, p, w, theta, theta_bar, mu, mu_bar, zeta, kappa, grad):

@@ -73,13 +73,13 @@ int64_t dirac_off(const fhs_plan *p) { return p->bands.back().off; }
 // and for the dual update 4P W row runs and 4P theta segments.
 int ana_lds_buf(const AnaArgs &a, int P) {
   int words = 2 * P * a.lds_row;
-  if (a.mode == 1) words += 4 * P * (kAnaLaneSeg + kAnaThSeg);
+  if (a.mode == 1 || a.mode == 3) words += 4 * P * (kAnaLaneSeg + kAnaThSeg);
   return words;
 }
 
 int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, const double *mu, double inv_kappa,
                  int mode, void *stream, int fy = -1, int fx = -1, int level = -1, bool with_dirac = true,
-                 const int32_t *active = nullptr) {
+                 const int32_t *active = nullptr, const uint8_t *sel = nullptr) {
   int tkx1, nth;
   if (int rc = thread_cfg(p, &tkx1, &nth, kAnaThreads)) return rc;
   const int TKX = tkx1;
@@ -103,9 +103,13 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     a.tky = p->tune.ana_rows[j];
     a.direct = (p->tune.ana_direct >> j) & 1;
     a.tile_major = (p->tune.ana_order >> j) & 1;
-    a.f32 = (mode == 1 && p->cfg.precision == FHS_PRECISION_MIXED) ? 1 : 0;
+    a.f32 = ((mode == 1 || mode == 3) && p->cfg.precision == FHS_PRECISION_MIXED) ? 1 : 0;
     a.mode = mode;
     a.active = active;
+    a.sel = sel;
+    a.own = static_cast<const uint8_t *>(ws_base(p)) + p->ws_own;
+    a.qy = p->cfg.qy;
+    a.qx = p->cfg.qx;
     // staged row: [sub-cube][column][lane slot], columns of the widest filter
     // (plus one pad column per sub-cube block when there are several), in
     // whole copy chunks (256 words with 16-byte copies, else 64)
@@ -137,6 +141,8 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       B.strips = std::max(0, ceil_div(B.kx_end - B.kx_begin, TKX));
       B.yblocks = std::max(0, ceil_div(B.ky_end - B.ky_begin, a.tky));
       B.ntap = p->ntap[b];
+      B.own_r = p->own_r[b][j];
+      B.own_c = p->own_c[b][j];
       for (int s = 0; s < 3; ++s) B.off[s] = coef_off(p, b, j, s);
       B.off[3] = j == levels - 1 ? ll_off(p, b) : -1;
       tmax = std::max(tmax, B.strips * B.yblocks);
@@ -166,6 +172,8 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
       D.in_ny = p->cfg.ny;
       D.in_nx = p->cfg.nx;
       D.off[0] = dirac_off(p);
+      D.own_r = p->own_dr;
+      D.own_c = p->own_dc;
       D.ky_begin = facet ? p->ty[fy] : 0;
       D.ky_end = facet ? p->ty[fy + 1] : p->cfg.ny;
       D.kx_begin = facet ? p->tx[fx] : 0;
@@ -331,7 +339,8 @@ int run_gather(const fhs_plan *p, const float *pdual, float *grad, double zeta, 
 // per-facet execution form.
 int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *theta_bar, const double *mu_bar,
                 double zeta, double *theta_bar_out, float *grad, float beta, int mode, void *stream,
-                bool no_gather = false, int q = -1, const int32_t *active = nullptr) {
+                bool no_gather = false, int q = -1, const int32_t *active = nullptr,
+                const uint8_t *sel = nullptr) {
   NucArgs a;
   std::memset(&a, 0, sizeof(a));
   fill_geom(p, a.g);
@@ -354,6 +363,7 @@ int run_nuclear(const fhs_plan *p, const float *x, float *pdual, const double *t
   a.q0 = q >= 0 ? q : 0;
   a.eig_q = q;
   a.active = active;
+  a.sel = mode == 0 ? sel : nullptr;
   const int nspatial = q >= 0 ? 1 : p->Q;
   const int nf = q >= 0 ? p->C : static_cast<int>(p->facets.size());
   int rc;
@@ -405,16 +415,34 @@ int l21_update(const fhs_plan *p, const float *xcheck, float *w, const float *th
                        active);
 }
 
+// The l21 dual update of the rows owned by the selected facets (randomized
+// step): the Dirac band is updated by the analysis (masked by tile), and the
+// synthesis reads every row as it stands.
+int l21_update_select(const fhs_plan *p, const float *xcheck, float *w, const float *theta, const double *mu,
+                      double kappa, float *grad, float beta, void *stream, const uint8_t *sel) {
+  if (int rc = run_analysis(p, xcheck, w, const_cast<float *>(theta), mu, 1.0 / kappa, 3, stream, -1, -1, -1, true,
+                            nullptr, sel))
+    return rc;
+  return run_synthesis(p, w, grad, static_cast<float>(kappa), beta, stream);
+}
+
+int l21_step(const fhs_plan *p, const float *xcheck, float *w, const float *theta, const double *mu, double kappa,
+             float *grad, void *stream, const int32_t *active, const uint8_t *sel) {
+  return sel ? l21_update_select(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream, sel)
+             : l21_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream, active);
+}
+
 }  // namespace
 
 namespace fhs {
 
 int facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, float *w, const float *theta,
                     const double *theta_bar, const double *mu, const double *mu_bar, double zeta, double kappa,
-                    float *grad, void *stream, const int32_t *active) {
+                    float *grad, void *stream, const int32_t *active, const uint8_t *sel) {
   if (!p->side || !p->tune.concurrent) {
-    if (int rc = l21_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream, active)) return rc;
-    return run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, stream, false, -1, active);
+    if (int rc = l21_step(p, xcheck, w, theta, mu, kappa, grad, stream, active, sel)) return rc;
+    return run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, stream, false, -1, active,
+                       sel);
   }
   // The two dual updates are independent until the gather: the nuclear
   // chain (Gram, eigendecomposition, reconstruction) runs on the plan's side
@@ -423,9 +451,9 @@ int facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, float 
   hipEvent_t fork = static_cast<hipEvent_t>(p->ev_fork), join = static_cast<hipEvent_t>(p->ev_join);
   if (hipEventRecord(fork, s0) != hipSuccess || hipStreamWaitEvent(s1, fork, 0) != hipSuccess)
     return fail(FHS_EHIP, "fork to the side stream failed");
-  int rc = run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, s1, true, -1, active);
+  int rc = run_nuclear(p, xcheck, pdual, theta_bar, mu_bar, zeta, nullptr, grad, 1.0f, 0, s1, true, -1, active, sel);
   const bool joined = hipEventRecord(join, s1) == hipSuccess;
-  if (rc == FHS_OK) rc = l21_update(p, xcheck, w, theta, mu, kappa, grad, 0.0f, stream, active);
+  if (rc == FHS_OK) rc = l21_step(p, xcheck, w, theta, mu, kappa, grad, stream, active, sel);
   if (!joined || hipStreamWaitEvent(s0, join, 0) != hipSuccess)
     return rc ? rc : fail(FHS_EHIP, "join of the side stream failed");
   if (rc) return rc;
@@ -480,6 +508,17 @@ int fhs_facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, fl
     return fail(FHS_EINVAL, "fhs_facet_prox_step: null array");
   if (!(zeta > 0) || !(kappa > 0)) return fail(FHS_EINVAL, "zeta and kappa must be positive");
   return facet_prox_step(p, xcheck, pdual, w, theta, theta_bar, mu, mu_bar, zeta, kappa, grad, stream, nullptr);
+}
+
+int fhs_facet_prox_step_select(const fhs_plan *p, const float *xcheck, float *pdual, float *w, const float *theta,
+                               const double *theta_bar, const double *mu, const double *mu_bar, double zeta,
+                               double kappa, const uint8_t *select, float *grad, void *stream) {
+  if (int rc = check_plan(p)) return rc;
+  if (!xcheck || !pdual || !w || !theta || !theta_bar || !mu || !mu_bar || !select || !grad)
+    return fail(FHS_EINVAL, "fhs_facet_prox_step_select: null array");
+  if (!(zeta > 0) || !(kappa > 0)) return fail(FHS_EINVAL, "zeta and kappa must be positive");
+  return facet_prox_step(p, xcheck, pdual, w, theta, theta_bar, mu, mu_bar, zeta, kappa, grad, stream, nullptr,
+                         select);
 }
 
 int fhs_facet_prox_step_plain(const fhs_plan *p, const float *xcheck, float *pdual, float *w, const float *theta,

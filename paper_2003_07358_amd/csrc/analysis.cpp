@@ -12,6 +12,7 @@ int launch_analysis(const AnaArgs &a, int nthreads, bool first, void *stream) {
     case 1: return a.f32 ? launch_analysis_m1f(a, nthreads, first, lds, stream)
                          : launch_analysis_m1(a, nthreads, first, lds, stream);
     case 2: return launch_analysis_m2(a, nthreads, first, lds, stream);
+    case 3: return launch_analysis_m3(a, nthreads, first, lds, stream);
     default: return fail(FHS_EINVAL, "analysis: unknown mode");
   }
 }

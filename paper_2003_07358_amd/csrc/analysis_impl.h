@@ -172,6 +172,15 @@ __device__ __forceinline__ void wait_vm_but(int n) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// Mode 3: bit sy set when facet (sy, sx) of sub-cube c is selected (at most
+// 64 facet rows).
+__device__ __forceinline__ uint64_t sel_bits(const AnaArgs &A, int c, int sx) {
+  uint64_t m = 0;
+  for (int sy = 0; sy < A.qy; ++sy)
+    if (A.sel[(c * A.qy + sy) * A.qx + sx] != 0) m |= uint64_t{1} << sy;
+  return m;
+}
+
 template <int NTAP, int MODE, int LCP, typename T>
 __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int tile, float *smem) {
   constexpr int H = NTAP / 2;
@@ -209,7 +218,7 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
   const uint32_t run_bytes = static_cast<uint32_t>(nkx * L * 4);  // one coefficient row run of the tile
   const uint64_t band_row = static_cast<uint64_t>(B.Kx) * L * 4;  // bytes per coefficient row of a band
   float thr = 0.0f;
-  if (MODE == 1) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
+  if (MODE == 1 || MODE == 3) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
   if (MODE == 2) thr = static_cast<float>(A.mu[c]);
   // a frozen sub-cube keeps its old W (mode 1) or theta (mode 2)
   const bool act = A.active == nullptr || A.active[c] != 0;
@@ -234,6 +243,9 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
   const int vo = ok ? wl * 4 : kOob;
   const int vth = ok ? static_cast<int>((static_cast<int64_t>(c) * A.I + kx0 + kq) * 4) : kOob;
   const int vth0 = lane == 0 ? vth : kOob;
+  // mode 3: bit sy of this lane's mask = facet (sy, owner column of its
+  // coefficient column) is selected
+  const uint64_t selbits = MODE == 3 && ok ? sel_bits(A, c, A.own[B.own_c + kx0 + kq]) : 0;
   // theta copy: word i = 64 j + ln of a segment -> (sub-cube i / TKX, column i % TKX)
   int th_voff[2];
 #pragma unroll
@@ -260,7 +272,7 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
   // one phase of copies: the 2P input rows (one wave each), and for the dual
   // update the W run and the theta values of each row emitted in the phase
   // (one wave per band and row), spread over the full waves
-  const int ntask = 2 * P + (MODE == 1 ? 8 * P : 0);
+  const int ntask = 2 * P + (MODE == 1 || MODE == 3 ? 8 * P : 0);
   auto issue_phase = [&](int ph) __attribute__((always_inline)) {
     float *buf = smem + (ph & 1) * A.lds_buf;
     for (int t = wv; t < ntask && wv < nwv; t += nwv) {
@@ -357,11 +369,12 @@ __device__ __forceinline__ void basis(const AnaArgs &A, const AnaBand &B, int ti
         if (sb == 3 && !last) continue;
         if (MODE == 0) {
           st_f32(vb[sb], rsrc(wbase[sb] + rb, run_bytes), vo, 0);
-        } else if (MODE == 1) {
+        } else if (MODE == 1 || MODE == 3) {
           const float wold = wsg[sb * kAnaLaneSeg], th = tsg[sb * kAnaThSeg];
           const float u = lane < Lc ? wold + vb[sb] : 0.0f;
           const float wn = shrink<LCP>(u, thr * th);
-          st_f32(act ? wn : wold, rsrc(wbase[sb] + rb, run_bytes), vo, 0);
+          const bool upd = MODE == 3 ? ((selbits >> A.own[B.own_r + ky]) & 1) != 0 : act;
+          st_f32(upd ? wn : wold, rsrc(wbase[sb] + rb, run_bytes), vo, 0);
         } else {
           const float r2 = seg_sum(vb[sb] * vb[sb], LCP);
           st_f32(thr / (sqrtf(r2) + thr), rsrc(A.theta, static_cast<uint32_t>(A.theta_bytes)), act ? vth0 : kOob,
@@ -423,9 +436,10 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
   const int nsteps = (ky1 - ky0) + H - 1;
   const int64_t rowlen = static_cast<int64_t>(B.in_nx) * L;
   float thr = 0.0f;
-  if (MODE == 1) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
+  if (MODE == 1 || MODE == 3) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
   if (MODE == 2) thr = static_cast<float>(A.mu[c]);
   const bool act = A.active == nullptr || A.active[c] != 0;  // frozen sub-cubes keep W / theta
+  const uint64_t selbits = MODE == 3 && ok ? sel_bits(A, c, A.own[B.own_c + kx]) : 0;
   // byte offset of tap NTAP-1 (column 2 kx + 2 - NTAP) of this lane in a row;
   // tap m adds (NTAP-1-m) L 4 (negative columns wrap to huge offsets: zeros,
   // as do columns past the row)
@@ -452,7 +466,7 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
 #pragma unroll
     for (int sb = 0; sb < 4; ++sb) {
       w[sb] = th[sb] = 0.0f;
-      if (MODE == 1) {
+      if (MODE == 1 || MODE == 3) {
         const int ky = ky0 + g - (H - 1);
         const bool v = ok && g < nsteps && ky >= ky0 && (sb < 3 || last);
         if (v) {
@@ -495,10 +509,11 @@ __device__ __forceinline__ void basis_direct(const AnaArgs &A, const AnaBand &B,
         const int64_t rowi = B.off[sb] + static_cast<int64_t>(ky) * B.Kx + kx;
         if (MODE == 0) {
           if (ok) A.w[rowi * L + p] = vb[sb];
-        } else if (MODE == 1) {
+        } else if (MODE == 1 || MODE == 3) {
           // (lanes past Lc load channel 0: kept out of the norm)
           const float wn = shrink<LCP>(lv ? w[sb] + vb[sb] : 0.0f, thr * th[sb]);
-          if (ok && act) A.w[rowi * L + p] = wn;
+          const bool upd = MODE == 3 ? ((selbits >> A.own[B.own_r + ky]) & 1) != 0 : act;
+          if (ok && upd) A.w[rowi * L + p] = wn;
         } else {
           const float vv = lv ? vb[sb] : 0.0f;
           const float r2 = seg_sum(vv * vv, LCP);
@@ -548,7 +563,7 @@ __global__ void __launch_bounds__(kDiracThreads) dirac_kernel(AnaArgs A) {
   const int64_t pix_first = static_cast<int64_t>(B.ky_begin) * B.in_nx + B.kx_begin;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * ppw;
   float thr = 0.0f;
-  if (MODE == 1) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
+  if (MODE == 1 || MODE == 3) thr = static_cast<float>(A.mu[c] * A.inv_kappa);
   if (MODE == 2) thr = static_cast<float>(A.mu[c]);
   const bool act = A.active == nullptr || A.active[c] != 0;  // frozen sub-cubes keep W / theta
   auto pixel = [&](int64_t li) { return full ? pix_first + li : pix_first + (li / rw) * B.in_nx + li % rw; };
@@ -560,8 +575,8 @@ __global__ void __launch_bounds__(kDiracThreads) dirac_kernel(AnaArgs A) {
       const int64_t pix = ok ? pixel(li) : 0;
       const int64_t i = B.off[0] + pix;
       v[e] = ok ? B.in[pix * L + chan] : 0.0f;
-      w[e] = (ok && MODE == 1) ? A.w[i * L + p] : 0.0f;
-      th[e] = (ok && MODE == 1) ? A.theta[c * A.I + i] : 0.0f;
+      w[e] = (ok && (MODE == 1 || MODE == 3)) ? A.w[i * L + p] : 0.0f;
+      th[e] = (ok && (MODE == 1 || MODE == 3)) ? A.theta[c * A.I + i] : 0.0f;
     }
   };
   const int64_t first = static_cast<int64_t>(blockIdx.x) * ppw + kq;
@@ -578,9 +593,16 @@ __global__ void __launch_bounds__(kDiracThreads) dirac_kernel(AnaArgs A) {
       const float x3 = v[e] * (1.0f / 3.0f);
       if (MODE == 0) {
         if (ok) A.w[i * L + p] = x3;
-      } else if (MODE == 1) {
+      } else if (MODE == 1 || MODE == 3) {
         const float nw = l21_row_update(w[e], v[e], thr * th[e], LCP);
-        if (ok && act) A.w[i * L + p] = nw;
+        bool upd = act;
+        if (MODE == 3 && ok) {
+          // the pixel's tile is the owner facet of its Dirac row
+          const int64_t pix = pixel(li), yy = pix / B.in_nx;
+          const int sy = A.own[B.own_r + yy], sx = A.own[B.own_c + (pix - yy * B.in_nx)];
+          upd = A.sel[(c * A.qy + sy) * A.qx + sx] != 0;
+        }
+        if (ok && upd) A.w[i * L + p] = nw;
       } else {
         const float r2 = seg_sum(x3 * x3, LCP);
         if (ok && act && lane == 0) A.theta[static_cast<int64_t>(c) * A.I + i] = thr / (sqrtf(r2) + thr);

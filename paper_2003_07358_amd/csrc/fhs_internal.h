@@ -49,6 +49,7 @@ struct AnaBand {
   int64_t off[4];      // first coefficient row of lh, hl, hh, ll (ll: last level, else -1)
   int ky_begin, ky_end, kx_begin, kx_end;  // coefficients computed (the whole band unless per facet);
                                             // for the Dirac band: the pixel rectangle
+  int32_t own_r, own_c;  // offsets in AnaArgs::own of the owner facet row of each coefficient row / column
 };
 
 struct AnaArgs {
@@ -60,7 +61,8 @@ struct AnaArgs {
   int64_t I;
   int64_t theta_bytes;        // C * I * 4 (< 2^31)
   int L, C, Lc, Lcp, tkx1, tky;
-  int mode;                   // 0: write Psi^dagger x; 1: l21 dual update; 2: l21 weights
+  int mode;                   // 0: write Psi^dagger x; 1: l21 dual update; 2: l21 weights;
+                              // 3: l21 dual update of the rows owned by selected facets only
   int P;                      // steps per LDS phase
   int lds_row;                // words per staged input row ([sub-cube][column][lane slot], 16-tap width)
   int lds_wv, lds_th;         // offsets (words) of the W and theta areas in a phase buffer
@@ -74,6 +76,9 @@ struct AnaArgs {
   int tile_major;             // launch order: 1 the 8 bases of a tile back to back, 0 basis-major
   int f32;                    // 1: FP32 accumulation of the filters (mixed-precision form, mode 1)
   const int32_t *active;      // [C] sub-cubes whose W (mode 1) or theta (mode 2) may change; null: all
+  const uint8_t *sel;         // mode 3: [C][Q] facets whose owned rows are updated
+  const uint8_t *own;         // mode 3: owner facet row / column tables (plan workspace)
+  int qy, qx;                 // facets per axis
 };
 
 // One wavelet basis at one level of the synthesis (levels >= 2): writes the
@@ -142,6 +147,7 @@ struct NucArgs {
   int q0;                    // first spatial facet of the launch (blockIdx.y offset)
   int eig_q;                 // -1: eig over all C*Q facets; else facets c*Q + eig_q, c < C
   const int32_t *active;     // [C] sub-cubes whose P (mode 0) or theta_bar (mode 1) may change; null: all
+  const uint8_t *sel;        // [C][Q] facets whose P is updated (mode 0), or null: all
   unsigned *diag;            // [2] counters: eigendecompositions not converged, non-finite Grams (or null)
 };
 
@@ -184,6 +190,7 @@ int launch_analysis_m0(const AnaArgs &a, int nthreads, bool first, size_t lds, v
 int launch_analysis_m1(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
 int launch_analysis_m1f(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
 int launch_analysis_m2(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
+int launch_analysis_m3(const AnaArgs &a, int nthreads, bool first, size_t lds, void *stream);
 int launch_synthesis(const SynArgs &a, int nthreads, void *stream);
 int launch_synthesis_final(const SynFinalArgs &a, int nthreads, int group, void *stream);
 int launch_nuc_gram(const NucArgs &a, int nspatial, void *stream);
@@ -199,7 +206,7 @@ int launch_snr(const SnrArgs &a, void *stream);
 // the closure, x, xcheck, v) bit for bit.
 int facet_prox_step(const fhs_plan *p, const float *xcheck, float *pdual, float *w, const float *theta,
                     const double *theta_bar, const double *mu, const double *mu_bar, double zeta, double kappa,
-                    float *grad, void *stream, const int32_t *active);
+                    float *grad, void *stream, const int32_t *active, const uint8_t *sel = nullptr);
 int reweight(const fhs_plan *p, const float *x, const double *upsilon, const double *upsilon_bar, float *theta,
              double *theta_bar, void *stream, const int32_t *active);
 // Workspace base of the compute sequences: the plan's, or the static scratch
@@ -229,11 +236,18 @@ struct fhs_plan {
   // per basis and level, the Q_axis + 1 boundaries of the coefficients each
   // facet owns (used by the per-facet execution form)
   std::vector<int> own_y[fhs::kBases][fhs::kMaxLevels], own_x[fhs::kBases][fhs::kMaxLevels];
+  // the same as tables (uint8 owner facet row of every coefficient row, owner
+  // facet column of every coefficient column; the Dirac band: the tiles),
+  // copied into the workspace at ws_own when it is attached
+  std::vector<uint8_t> own_tab;
+  int32_t own_r[fhs::kBases][fhs::kMaxLevels], own_c[fhs::kBases][fhs::kMaxLevels];
+  int32_t own_dr = 0, own_dc = 0;
   float h[fhs::kBases][fhs::kMaxTap], g[fhs::kBases][fhs::kMaxTap];
   int ntap[fhs::kBases];
   // workspace layout (bytes)
   int64_t ws_ll[fhs::kBases][fhs::kMaxLevels];
-  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_red = 0, ws_factor = 0, ws_ctl = 0, ws_active = 0, ws_diag = 0;
+  int64_t ws_gram = 0, ws_kmat = 0, ws_sig = 0, ws_red = 0, ws_factor = 0, ws_ctl = 0, ws_active = 0, ws_diag = 0,
+          ws_own = 0;
   int64_t ws_bytes = 0;
   int64_t red_ppb = 0;                     // closure: pixels per block
   int red_blocks = 0;                      // closure: blocks

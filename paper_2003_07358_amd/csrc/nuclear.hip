@@ -159,6 +159,11 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
   const bool with_p = A.p != nullptr;
   const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const int c0 = blockIdx.z * K, nc = min(K, g.C - c0);
+  if (A.sel != nullptr) {  // randomized step: no selected facet among these sub-cubes
+    bool any = false;
+    for (int kc = 0; kc < nc; ++kc) any = any || A.sel[(c0 + kc) * Q + q] != 0;
+    if (!any) return;
+  }
   using Acc = typename std::conditional<BF16, v4f, v4d>::type;
   Acc acc[K][PR::n];
 #pragma unroll
@@ -298,6 +303,7 @@ __global__ void __launch_bounds__(kEigThreads) nuc_eig_kernel(NucArgs A) {
   const int f = A.eig_q < 0 ? blockIdx.x : blockIdx.x * (g.qy * g.qx) + A.eig_q;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int n = g.Lc, n2 = n + (n & 1);
+  if (A.sel != nullptr && A.sel[f] == 0) return;  // randomized step: facet not selected
   const FacetView F = facet_view(g, f);
   const int nch = (F.hy + A.chunk_wrows - 1) / A.chunk_wrows;
   const double *gp = A.gram + static_cast<int64_t>(f) * A.chunks * A.lc16 * A.lc16;
@@ -482,6 +488,7 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
     const int nfl = sg.n * Lc;
     for (int c = 0; c < C; ++c) {
       if (A.active != nullptr && A.active[c] == 0) continue;  // a frozen sub-cube keeps its P
+      if (A.sel != nullptr && A.sel[c * Q + q] == 0) continue;  // an unselected facet keeps its P
       float *dst = A.p + c * g.p_sub + F.poff + (static_cast<int64_t>(sg.y) * F.hx + sg.s0) * Lc;
       for (int e = threadIdx.x; e < nfl; e += blockDim.x) dst[e] = outt[c * S * Lc + e];
     }
@@ -520,6 +527,7 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   if (y0 >= F.hy) return;
   const int y1 = min(y0 + A.chunk_wrows, F.hy);
   if (A.active != nullptr && A.active[0] == 0) return;  // the one sub-cube is frozen: P stays
+  if (A.sel != nullptr && A.sel[q] == 0) return;        // an unselected facet keeps its P
   const int S = A.seg, L = g.L, Lc = g.Lc;
   const int Lp = recon1_stride(L);
   const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;

@@ -195,6 +195,31 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   p->bands.push_back({c.ny, c.nx, off, 0});
   off += static_cast<int64_t>(c.ny) * c.nx;
   p->I = off;
+  // owner tables of the randomized step: facet row / column owning each
+  // coefficient row / column of every basis and level, and each pixel row /
+  // column of the Dirac band (its tile)
+  {
+    auto append = [&](const std::vector<int> &bounds, int n) {
+      const int32_t at = static_cast<int32_t>(p->own_tab.size());
+      for (int s = 0; s + 1 < static_cast<int>(bounds.size()); ++s)
+        for (int i = bounds[s]; i < bounds[s + 1]; ++i) p->own_tab.push_back(static_cast<uint8_t>(s));
+      if (static_cast<int32_t>(p->own_tab.size()) - at != n) return -1;
+      return static_cast<int>(at);
+    };
+    bool okt = true;
+    for (int b = 0; b < kBases; ++b)
+      for (int j = 0; j < c.levels; ++j) {
+        p->own_r[b][j] = append(p->own_y[b][j], p->Ky[b][j]);
+        p->own_c[b][j] = append(p->own_x[b][j], p->Kx[b][j]);
+        okt = okt && p->own_r[b][j] >= 0 && p->own_c[b][j] >= 0;
+      }
+    p->own_dr = append(p->ty, c.ny);
+    p->own_dc = append(p->tx, c.nx);
+    if (!okt || p->own_dr < 0 || p->own_dc < 0) {
+      delete p;
+      return fail(FHS_EINVAL, "internal: ownership does not cover the bands");
+    }
+  }
   if (static_cast<int64_t>(p->C) * p->I * 4 >= (int64_t{1} << 31)) {
     delete p;
     return fail(FHS_EUNSUPPORTED, "theta (C * I floats) must be smaller than 2 GiB");
@@ -264,6 +289,9 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   // diagnostic counters (cleared when the workspace is attached)
   p->ws_diag = ws;
   ws = align256(ws + 2 * 4);
+  // owner tables (copied when the workspace is attached)
+  p->ws_own = ws;
+  ws = align256(ws + static_cast<int64_t>(p->own_tab.size()));
   p->ws_bytes = ws;
   *out = p;
   return FHS_OK;
@@ -369,8 +397,10 @@ int fhs_plan_set_workspace(fhs_plan *p, void *dev_ptr, int64_t bytes) {
   p->ws = dev_ptr;
   p->ws_given = bytes;
   if (hipMemset(static_cast<char *>(dev_ptr) + p->ws_diag, 0, 2 * sizeof(unsigned)) != hipSuccess ||
+      hipMemcpy(static_cast<char *>(dev_ptr) + p->ws_own, p->own_tab.data(), p->own_tab.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess)
-    return fail(FHS_EHIP, "fhs_plan_set_workspace: clearing the diagnostic counters failed");
+    return fail(FHS_EHIP, "fhs_plan_set_workspace: initialising the workspace failed");
   if (!p->side) {
     // side stream (default priority) and fork / join events for the
     // concurrent nuclear chain; without them the step runs on one stream
