@@ -22,6 +22,10 @@ against the paper by eye:
                     dual update, the weighted l21 dual update and the gather
                     into the primal gradient (facet part of the aggregation);
                     its randomized form updates a random subset of facets.
+* ``spectral``   -- the facet step with overlapping spectral facets (the
+                    100-channel case read literally: contiguous blocks whose
+                    low-rankness facets overlap by a few channels with a
+                    triangular spectral ramp; a reading, not in the paper).
 * ``heuristics`` -- regularisation parameters (eqs. heuristic_fhs_sparsity and
                     heuristic_fhs_low_rank) and reweighting weights
                     (eqs. facet_hypersara_rank and facet_hypersara_sparsity).
