@@ -88,6 +88,20 @@ typedef struct {
   int32_t overlap_x;     /* ... toward the left                                      */
   int32_t levels;        /* wavelet decomposition levels (1..6; 4 in the paper)      */
   int32_t precision;     /* FHS_PRECISION_FP32 (0) or FHS_PRECISION_MIXED (1)         */
+  int32_t spectral_overlap; /* o: 0 = the paper's interleaved, independent sub-cubes.
+                            o > 0 (a reading beyond the paper, FP32 form, C >= 2,
+                            o <= L/C): C contiguous blocks of L/C channels (the l21
+                            rows), each low-rankness facet also taking the o channels
+                            before its block, with the spatial window's triangular
+                            ramp applied along channels (Sec. 2.4.2 rule on the
+                            spectral axis), so the blocks' weights sum to one per
+                            channel.  A facet's P then has L/C + o columns, the
+                            window's channels in order; for the first block the
+                            first o columns lie before channel 0 and are structural
+                            zeros (pass zeros; they stay zero).  theta_bar likewise
+                            has L/C + o weights per facet (for the first block the
+                            first L/C apply).  The sub-cubes are no longer
+                            independent: the PDFB closure and solve reject it.     */
 } fhs_config;
 
 typedef struct {
@@ -97,7 +111,8 @@ typedef struct {
   int64_t n_w;              /* floats of W: I * L                              */
   int64_t n_theta;          /* floats of theta: C * I                          */
   int64_t n_facets;         /* C * Q                                           */
-  int64_t n_theta_bar;      /* doubles of theta_bar: C * Q * L_c               */
+  int64_t n_theta_bar;      /* doubles of theta_bar: C * Q * L_c (+ o, see
+                               spectral_overlap)                                */
   int64_t n_bands;          /* bands of Psi^dagger: 8 * (3 levels + 1) + 1     */
   int64_t workspace_bytes;  /* bytes for fhs_plan_set_workspace                */
 } fhs_sizes;

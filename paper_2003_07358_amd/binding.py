@@ -20,7 +20,8 @@ class FhsError(RuntimeError):
 
 class _Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("ny", "nx", "nchan", "qy", "qx", "n_sub", "overlap_y", "overlap_x", "levels", "precision")]
+                ("ny", "nx", "nchan", "qy", "qx", "n_sub", "overlap_y", "overlap_x", "levels", "precision",
+                 "spectral_overlap")]
 
 
 class _Sizes(ctypes.Structure):
@@ -172,10 +173,14 @@ def _stream(t):
 class Plan:
     """Geometry of one problem (include/fhs.h, fhs_plan_create) plus its workspace."""
 
-    def __init__(self, ny, nx, nchan, qy=1, qx=1, n_sub=1, overlap_y=0, overlap_x=0, levels=4, precision=0):
-        """precision: 0 = FHS_PRECISION_FP32, 1 = FHS_PRECISION_MIXED (include/fhs.h)."""
+    def __init__(self, ny, nx, nchan, qy=1, qx=1, n_sub=1, overlap_y=0, overlap_x=0, levels=4, precision=0,
+                 spectral_overlap=0):
+        """precision: 0 = FHS_PRECISION_FP32, 1 = FHS_PRECISION_MIXED; spectral_overlap: channels
+        by which the low-rankness facets of contiguous sub-cubes overlap (0: interleaved
+        sub-cubes), see include/fhs.h."""
         self._lib = lib()
-        self.cfg = _Config(ny, nx, nchan, qy, qx, n_sub, overlap_y, overlap_x, levels, precision)
+        self.cfg = _Config(ny, nx, nchan, qy, qx, n_sub, overlap_y, overlap_x, levels, precision,
+                           spectral_overlap)
         handle = ctypes.c_void_p()
         _check(self._lib.fhs_plan_create(ctypes.byref(self.cfg), ctypes.byref(handle)))
         self._p = handle
@@ -187,6 +192,8 @@ class Plan:
         self.Q = qy * qx
         self.levels = levels
         self.precision = precision
+        self.spectral_overlap = spectral_overlap
+        self.Ln = self.Lc + spectral_overlap  # columns of a facet matrix
         self.workspace = None
 
     def __del__(self):

@@ -116,7 +116,7 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     a.vec4 = (p->L % 4 == 0 && p->Lc % 4 == 0) ? 1 : 0;
     // (the kernel copies 4 bytes per lane from the natural-order cube when
     // there are several sub-cubes: a sub-cube's channels are not contiguous)
-    const bool v4 = a.vec4 && (p->C == 1 || j > 0);
+    const bool v4 = a.vec4 && (p->C == 1 || j > 0 || p->so > 0);
     const int cw = v4 ? 256 : 64;
     const int ncp = 2 * TKX + kMaxTap - 2 + (p->C > 1 ? 1 : 0);
     const int nchunk = ceil_div(static_cast<int64_t>(p->C) * ncp * p->Lcp, cw);
@@ -128,7 +128,8 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     for (int b = 0; b < kBases; ++b) {
       AnaBand &B = a.b[b];
       B.in = j == 0 ? x : ws_f(p, p->ws_ll[b][j - 1]);
-      B.in_natural = j == 0 ? 1 : 0;
+      // (contiguous sub-cubes: the cube's channel order is the positions order)
+      B.in_natural = j == 0 && p->so == 0 ? 1 : 0;
       B.in_ny = p->in_ny[b][j];
       B.in_nx = p->in_nx[b][j];
       B.ll_out = j < levels - 1 ? ws_f(p, p->ws_ll[b][j]) : nullptr;
@@ -168,7 +169,7 @@ int run_analysis(const fhs_plan *p, const float *x, float *w, float *theta, cons
     if (j == 0) {
       AnaBand &D = a.b[kBases];
       D.in = x;
-      D.in_natural = 1;
+      D.in_natural = p->so == 0 ? 1 : 0;
       D.in_ny = p->cfg.ny;
       D.in_nx = p->cfg.nx;
       D.off[0] = dirac_off(p);
@@ -280,6 +281,7 @@ int run_synthesis(const fhs_plan *p, const float *w, float *x, float alpha, floa
   f.theta_bytes = static_cast<int64_t>(p->C) * p->I * 4;
   f.alpha = alpha;
   f.beta = beta;
+  f.contig = p->so > 0 ? 1 : 0;
   f.ny = p->cfg.ny;
   f.nx = p->cfg.nx;
   f.L = L;
@@ -311,7 +313,10 @@ void fill_geom(const fhs_plan *p, NucGeom &g) {
   g.nx = p->cfg.nx;
   g.L = p->L;
   g.C = p->C;
-  g.Lc = p->Lc;
+  g.Lc = p->Ln;
+  g.spec = p->so > 0 ? 1 : 0;
+  g.sb = p->Lc;
+  g.so = p->so;
   g.qy = p->cfg.qy;
   g.qx = p->cfg.qx;
   g.oy = p->cfg.overlap_y;

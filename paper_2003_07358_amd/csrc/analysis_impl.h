@@ -556,7 +556,7 @@ __global__ void __launch_bounds__(kDiracThreads) dirac_kernel(AnaArgs A) {
   const int ppw = dense_width(LCP) ? dense_segments(blockDim.x, LCP) / C : blockDim.x / (C * LCP);
   const bool lv = !idle && lane < Lc && kq < ppw;
   const int p = c * Lc + lane;
-  const int chan = lv ? c + lane * C : 0;
+  const int chan = lv ? (B.in_natural ? c + lane * C : p) : 0;
   const int rw = B.kx_end - B.kx_begin;
   const bool full = rw == B.in_nx;
   const int64_t npix = static_cast<int64_t>(B.ky_end - B.ky_begin) * rw;

@@ -90,8 +90,9 @@ __global__ void __launch_bounds__(kThreads) closure_primal(ClosureArgs a) {
   double dx2 = 0.0, x2 = 0.0;
   if (t < G * L) {
     const int g = t / L, l = t - (t / L) * L;
-    // channel l belongs to sub-cube l mod C; a frozen sub-cube keeps x, xcheck, v
-    const bool act = a.active == nullptr || a.active[l % a.C] != 0;
+    // channel l belongs to sub-cube l mod C (l / L_c for contiguous blocks);
+    // a frozen sub-cube keeps x, xcheck, v
+    const bool act = a.active == nullptr || a.active[a.contig ? l / (L / a.C) : l % a.C] != 0;
     const double f = a.factor[l];
     const double tau = a.tau;
     for (int64_t p = p0 + g; p < p1; p += G) {
@@ -145,7 +146,8 @@ __global__ void __launch_bounds__(kThreads) closure_xi(ClosureArgs a) {
   __syncthreads();
   if (t < a.C) {
     double a0 = 0.0, a1 = 0.0;
-    for (int l = t; l < L; l += a.C) {
+    const int l0 = a.contig ? t * (L / a.C) : t, l1 = a.contig ? l0 + L / a.C : L, dl = a.contig ? 1 : a.C;
+    for (int l = l0; l < l1; l += dl) {
       a0 += ch0[l];
       a1 += ch1[l];
     }

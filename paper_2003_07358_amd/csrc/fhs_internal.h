@@ -115,13 +115,19 @@ struct SynFinalArgs {
   int64_t theta_bytes;        // C * I * 4 (< 2^31)
   const int32_t *active;      // [C] sub-cubes whose Dirac rows the fused update may change; null: all
   float alpha, beta;
+  int contig;                 // 1: sub-cube c holds the contiguous channels [c Lc, (c + 1) Lc)
   int ny, nx, L, Lcp, C, Lc, tk, ty, strips, yblocks;
   int y_begin, y_end, x_begin, x_end;  // output pixels computed (all unless per facet)
 };
 
 // Facet geometry for the nuclear kernels (Sec. 2.4.2).
 struct NucGeom {
-  int ny, nx, L, C, Lc, qy, qx, oy, ox;
+  int ny, nx, L, C, Lc, qy, qx, oy, ox;  // Lc: columns of a facet matrix
+  // spectral layout: spec 0 = interleaved sub-cubes (column ch of sub-cube c
+  // is channel c + ch C); spec 1 = contiguous blocks of sb channels whose
+  // facet columns start so channels before the block (channel c sb - so + ch,
+  // weighted by the spectral ramp)
+  int spec, sb, so;
   int ty[kMaxFacetAxis + 1], tx[kMaxFacetAxis + 1];  // tile bounds
   int py[kMaxFacetAxis + 1], px[kMaxFacetAxis + 1];  // prefix sums of window heights / widths
   int64_t p_sub;  // floats of P per sub-cube
@@ -172,6 +178,7 @@ struct ClosureArgs {
   double tau;
   int64_t npix, ppb;   // pixels, pixels per block
   int L, C, nblocks;
+  int contig;          // 1: sub-cube c holds the contiguous channels [c L / C, (c + 1) L / C)
 };
 
 struct SnrArgs {
@@ -219,6 +226,7 @@ void *ws_base(const fhs_plan *p);
 struct fhs_plan {
   fhs_config cfg{};
   int L = 0, C = 1, Lc = 0, Q = 0, Lcp = 0, lc16 = 0;
+  int so = 0, Ln = 0;                      // spectral overlap; columns of a facet matrix (Lc + so)
   std::vector<int> ty, tx;                 // tile bounds
   struct Facet {
     int c, sy, sx, ty0, ty1, tx0, tx1, wy0, wy1, wx0, wx1;

@@ -88,7 +88,21 @@ __device__ __forceinline__ Seg seg_of(int i, int y0, int nsx, int S, int hx) {
 }
 
 // words of one staging buffer: X [S][L] then P [C][S][L_c]
-__device__ __forceinline__ int stage_words(int S, int L) { return 2 * S * L; }
+__device__ __forceinline__ int stage_words(const NucGeom &g, int S) { return S * (g.L + g.C * g.Lc); }
+
+// Overlapping spectral facets (contiguous blocks): channel of column ch of
+// block c (negative before the cube: a structural-zero column of the first
+// block) and its spectral weight, the triangular ramp of the spatial window
+// (Sec. 2.4.2) on the channel axis: rising over the so columns before the
+// block (not for the first block), falling over the block's last so columns
+// (not for the last block).
+__device__ __forceinline__ int spec_chan(const NucGeom &g, int c, int ch) { return c * g.sb - g.so + ch; }
+__device__ __forceinline__ double spec_weight(const NucGeom &g, int c, int ch) {
+  if (c > 0 && ch < g.so) return static_cast<double>(ch + 1) / static_cast<double>(g.so + 1);
+  if (c < g.C - 1 && ch >= g.Lc - g.so)
+    return 1.0 - static_cast<double>(ch - (g.Lc - g.so) + 1) / static_cast<double>(g.so + 1);
+  return 1.0;
+}
 
 __device__ __forceinline__ void issue_seg(const NucArgs &A, const FacetView &F, const Seg &sg, float *buf, double *dsh,
                                           bool with_p) {
@@ -106,15 +120,22 @@ __device__ __forceinline__ void issue_seg(const NucArgs &A, const FacetView &F, 
 }
 
 // Z_c[r][ch] = P_c[r][ch] + D_r X[r][c + ch C] in FP64 (0 outside the segment
-// and beyond L_c).
+// and beyond L_c); SPEC: + D_r d_c(ch) X[r][c sb - so + ch] (overlapping
+// spectral facets; P alone on structural-zero columns).
+template <bool SPEC>
 __device__ __forceinline__ double zval(const NucArgs &A, const float *buf, const double *dsh, int n, bool with_p,
                                        int c, int r, int ch) {
   const NucGeom &g = A.g;
   if (r >= n || ch >= g.Lc) return 0.0;
   const int S = A.seg, L = g.L;
-  const double xv = static_cast<double>(buf[r * L + c + ch * g.C]);
   const double pv = with_p ? static_cast<double>(buf[S * L + (c * S + r) * g.Lc + ch]) : 0.0;
-  return fma(dsh[r], xv, pv);
+  if constexpr (SPEC) {
+    const int chan = spec_chan(g, c, ch);
+    return chan >= 0 ? fma(dsh[r] * spec_weight(g, c, ch), static_cast<double>(buf[r * L + chan]), pv) : pv;
+  } else {
+    const double xv = static_cast<double>(buf[r * L + c + ch * g.C]);
+    return fma(dsh[r], xv, pv);
+  }
 }
 
 constexpr int kMaxSeg = 64;  // pixels per segment (upper bound)
@@ -142,8 +163,9 @@ constexpr int gram_subcubes() {
 // 16 rows (lane l holds rows 4 (l / 16) .. + 3 of its channel l mod 16: the
 // same operand serves as A = Z^T and B = Z, as in the FP64 form); the
 // partials are summed across waves in FP64.
-template <int NB, int K, bool BF16>
+template <int NB, int K, bool BF16, bool SPEC = false>
 __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
+  static_assert(!(BF16 && SPEC), "overlapping spectral facets run in the FP32 form only");
   using PR = Pairs<NB>;
   extern __shared__ float sm[];
   __shared__ double dsh[2][kMaxSeg];
@@ -155,7 +177,7 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
   const int y1 = min(y0 + A.chunk_wrows, F.hy);
   const int S = A.seg, L = g.L;
   const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;
-  const int BUF = stage_words(S, L);
+  const int BUF = stage_words(g, S);
   const bool with_p = A.p != nullptr;
   const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const int c0 = blockIdx.z * K, nc = min(K, g.C - c0);
@@ -217,14 +239,19 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
           if (kc < nc) {
             // Z[r][ch] = P_c[r][ch] + D_r X[r][c + ch C], ch = 16 b + (ln % 16)
             const int c = c0 + kc, ch0 = ln & 15;
-            const float *xr = buf + r * L + c + ch0 * g.C;
             const float *pr = buf + S * L + (c * S + r) * g.Lc + ch0;
             double z[NB];
+            if constexpr (SPEC) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              const bool ok = rv && 16 * b + ch0 < g.Lc;
-              const double pv = with_p ? static_cast<double>(pr[16 * b]) : 0.0;
-              z[b] = ok ? fma(dr, static_cast<double>(xr[16 * b * g.C]), pv) : 0.0;
+              for (int b = 0; b < NB; ++b) z[b] = rv ? zval<true>(A, buf, d, n, with_p, c, r, 16 * b + ch0) : 0.0;
+            } else {
+              const float *xr = buf + r * L + c + ch0 * g.C;
+#pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                const bool ok = rv && 16 * b + ch0 < g.Lc;
+                const double pv = with_p ? static_cast<double>(pr[16 * b]) : 0.0;
+                z[b] = ok ? fma(dr, static_cast<double>(xr[16 * b * g.C]), pv) : 0.0;
+              }
             }
             int t = 0;
 #pragma unroll
@@ -418,7 +445,7 @@ __global__ void __launch_bounds__(kEigThreads) nuc_eig_kernel(NucArgs A) {
 // Gram kernel).  Work items (sub-cube, 16-row block, 16-channel block) are
 // spread over the waves; each is NB * 4 FP64 MFMAs with K_c read from LDS.
 // The result goes to an LDS tile first and then to HBM as contiguous runs.
-template <int NB>
+template <int NB, bool SPEC = false>
 __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
   constexpr int W = NB * 16;
   extern __shared__ float sm[];
@@ -431,7 +458,7 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
   const int y1 = min(y0 + A.chunk_wrows, F.hy);
   const int S = A.seg, L = g.L, Lc = g.Lc, C = g.C;
   const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;
-  const int BUF = stage_words(S, L);
+  const int BUF = stage_words(g, S);
   // LDS: K_c [C][W][W + 1] doubles, then two staging buffers, then the output tile [C][S][Lc]
   double *Ks = reinterpret_cast<double *>(sm);
   float *stage = sm + 2 * C * W * (W + 1);
@@ -462,7 +489,7 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
       const int r = 16 * nb + (ln & 15);
       double z[W / 4];
 #pragma unroll
-      for (int kk = 0; kk < W / 4; ++kk) z[kk] = zval(A, buf, d, sg.n, true, c, r, 4 * kk + ln / 16);
+      for (int kk = 0; kk < W / 4; ++kk) z[kk] = zval<SPEC>(A, buf, d, sg.n, true, c, r, 4 * kk + ln / 16);
 #pragma unroll
       for (int mb = 0; mb < NB; ++mb) {
         if (mb < mb0 || mb >= mb1) continue;
@@ -628,8 +655,12 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
 // weight and the offset of the pixel's row in each facet's P (sub-cube 0).
 // Then thread t works on channel t % L of pixels t / L, t / L + 256 / L, ...:
 // every P read and the gradient update are coalesced across the channels.
+// SPEC (overlapping spectral facets): channel ch is column ch - (c sb - so)
+// of its block c and, when it lies in the next block's leading so channels,
+// of that block too, each weighted by its spectral ramp.
 constexpr int kGatherPx = 256;
 
+template <bool SPEC>
 __global__ void __launch_bounds__(256) nuc_gather_kernel(GatherArgs A) {
   __shared__ double dk[kGatherPx][4];
   __shared__ int64_t rk[kGatherPx][4];
@@ -664,19 +695,37 @@ __global__ void __launch_bounds__(256) nuc_gather_kernel(GatherArgs A) {
   const int L = g.L, per = 256 / L;  // pixels per pass of the workgroup (L <= 256)
   const int t = threadIdx.x;
   if (t >= per * L) return;
-  const int ch = t % L, c = ch % g.C, l = ch / g.C;
-  const float *pc = A.p + c * g.p_sub + l;
+  const int ch = t % L;
+  const float *pc, *pc2 = nullptr;
+  double w1 = 1.0, w2 = 0.0;
+  if constexpr (SPEC) {
+    const int c1 = min(ch / g.sb, g.C - 1), col1 = ch - spec_chan(g, c1, 0);
+    pc = A.p + c1 * g.p_sub + col1;
+    w1 = spec_weight(g, c1, col1);
+    if (c1 + 1 < g.C && ch >= spec_chan(g, c1 + 1, 0)) {
+      const int col2 = ch - spec_chan(g, c1 + 1, 0);
+      pc2 = A.p + (c1 + 1) * g.p_sub + col2;
+      w2 = spec_weight(g, c1 + 1, col2);
+    }
+  } else {
+    const int c = ch % g.C, l = ch / g.C;
+    pc = A.p + c * g.p_sub + l;
+  }
   float *grow = A.grad + (static_cast<int64_t>(y) * g.nx + x0) * L + ch;
   // U pixels per thread in flight: all their loads are issued before the first use
   constexpr int U = 4;
   for (int i0 = t / L; i0 < npx; i0 += U * per) {
-    float pv[U][4], gv[U];
+    float pv[U][4], pv2[U][4], gv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * per;
       const bool ok = i < npx;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) pv[u][k] = (ok && dk[ok ? i : 0][k] != 0.0) ? pc[rk[i][k]] : 0.0f;
+      for (int k = 0; k < 4; ++k) {
+        const bool cov = ok && dk[ok ? i : 0][k] != 0.0;
+        pv[u][k] = cov ? pc[rk[i][k]] : 0.0f;
+        pv2[u][k] = (SPEC && cov && pc2 != nullptr) ? pc2[rk[i][k]] : 0.0f;
+      }
       gv[u] = (ok && A.beta != 0.0f) ? grow[static_cast<int64_t>(i) * L] : 0.0f;
     }
 #pragma unroll
@@ -685,7 +734,12 @@ __global__ void __launch_bounds__(256) nuc_gather_kernel(GatherArgs A) {
       if (i < npx) {
         double sum = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) sum += dk[i][k] * static_cast<double>(pv[u][k]);
+        for (int k = 0; k < 4; ++k) {
+          if constexpr (SPEC)
+            sum += dk[i][k] * (w1 * static_cast<double>(pv[u][k]) + w2 * static_cast<double>(pv2[u][k]));
+          else
+            sum += dk[i][k] * static_cast<double>(pv[u][k]);
+        }
         const float v = static_cast<float>(A.zeta * sum);
         grow[static_cast<int64_t>(i) * L] = A.beta != 0.0f ? fmaf(A.beta, gv[u], v) : v;
       }
@@ -703,10 +757,11 @@ static int check_launch(const char *what) {
 size_t nuc_lds_bytes(const NucArgs &a, bool recon) {
   const int W = a.lc16;
   // (+64 words: masked-out lanes read up to 63 words past a buffer)
-  const size_t stage = static_cast<size_t>(2 * 2 * a.seg * a.g.L + 64) * sizeof(float);
+  const size_t pw = static_cast<size_t>(a.g.C) * a.g.Lc;  // P floats per pixel over the sub-cubes
+  const size_t stage = (2 * static_cast<size_t>(a.seg) * (a.g.L + pw) + 64) * sizeof(float);
   if (!recon) return stage > 8192 ? stage : 8192;  // the unit reduction reuses it (4 x 256 doubles)
   return static_cast<size_t>(a.g.C) * W * (W + 1) * sizeof(double) + stage +
-         static_cast<size_t>(a.seg * a.g.L) * sizeof(float);
+         static_cast<size_t>(a.seg) * pw * sizeof(float);
 }
 
 int launch_nuc_gram(const NucArgs &a, int nspatial, void *stream) {
@@ -721,6 +776,13 @@ int launch_nuc_gram(const NucArgs &a, int nspatial, void *stream) {
       else                                                                                              \
         hipLaunchKernelGGL((nuc_gram_kernel<NB, KM, true>), dim3(a.chunks, nspatial, (a.g.C + KM - 1) / KM), \
                            dim3(256), lds, s, a);                                                       \
+    } else if (a.g.spec) {                                                                              \
+      if (KM == 1)                                                                                      \
+        hipLaunchKernelGGL((nuc_gram_kernel<NB, 1, false, true>), dim3(a.chunks, nspatial, a.g.C), dim3(256), lds, s, \
+                           a);                                                                          \
+      else                                                                                              \
+        hipLaunchKernelGGL((nuc_gram_kernel<NB, KM, false, true>),                                      \
+                           dim3(a.chunks, nspatial, (a.g.C + KM - 1) / KM), dim3(256), lds, s, a);      \
     } else if (a.g.C == 1 || KM == 1) {                                                                 \
       hipLaunchKernelGGL((nuc_gram_kernel<NB, 1, false>), dim3(a.chunks, nspatial, a.g.C), dim3(256), lds, s, a); \
     } else {                                                                                            \
@@ -762,6 +824,16 @@ int launch_nuc_recon(const NucArgs &a, int nspatial, void *stream) {
   }
   const size_t lds = nuc_lds_bytes(a, true);
   if (lds > 160 * 1024) return fail(FHS_EUNSUPPORTED, "reconstruction tile exceeds the LDS");
+  if (a.g.spec) {
+    switch (a.lc16 / 16) {
+      case 1: hipLaunchKernelGGL((nuc_recon_kernel<1, true>), grid, dim3(256), lds, s, a); break;
+      case 2: hipLaunchKernelGGL((nuc_recon_kernel<2, true>), grid, dim3(256), lds, s, a); break;
+      case 3: hipLaunchKernelGGL((nuc_recon_kernel<3, true>), grid, dim3(256), lds, s, a); break;
+      case 4: hipLaunchKernelGGL((nuc_recon_kernel<4, true>), grid, dim3(256), lds, s, a); break;
+      default: return fail(FHS_EUNSUPPORTED, "more than 64 channels per facet matrix");
+    }
+    return check_launch("nuc_recon");
+  }
   switch (a.lc16 / 16) {
     case 1: hipLaunchKernelGGL(nuc_recon_kernel<1>, grid, dim3(256), lds, s, a); break;
     case 2: hipLaunchKernelGGL(nuc_recon_kernel<2>, grid, dim3(256), lds, s, a); break;
@@ -775,7 +847,10 @@ int launch_nuc_recon(const NucArgs &a, int nspatial, void *stream) {
 int launch_nuc_gather(const GatherArgs &a, void *stream) {
   if (a.g.L > 256) return fail(FHS_EUNSUPPORTED, "gather: more than 256 channels");
   const dim3 grid((a.x_end - a.x_begin + kGatherPx - 1) / kGatherPx, a.y_end - a.y_begin);
-  hipLaunchKernelGGL(nuc_gather_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), a);
+  if (a.g.spec)
+    hipLaunchKernelGGL(nuc_gather_kernel<true>, grid, dim3(256), 0, static_cast<hipStream_t>(stream), a);
+  else
+    hipLaunchKernelGGL(nuc_gather_kernel<false>, grid, dim3(256), 0, static_cast<hipStream_t>(stream), a);
   return check_launch("nuc_gather");
 }
 

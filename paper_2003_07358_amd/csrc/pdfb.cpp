@@ -39,6 +39,7 @@ int closure(const fhs_plan *p, float *x, float *xcheck, float *v, const float *y
   a.L = p->L;
   a.C = p->C;
   a.nblocks = p->red_blocks;
+  a.contig = p->so > 0 ? 1 : 0;
   prof_begin(p, FHS_K_CLOSURE, stream);
   const int rc = launch_closure(a, stream);
   prof_end(p, FHS_K_CLOSURE, stream);
@@ -130,6 +131,8 @@ int fhs_reweighting_solve(const fhs_plan *p, const fhs_pdfb_state *s, const doub
   if (!p->ws) return fail(FHS_ENOWORKSPACE, "no workspace attached (fhs_plan_set_workspace)");
   if (int rc = check_state(s)) return rc;
   if (!upsilon || !upsilon_bar || !x_prev || !prm) return fail(FHS_EINVAL, "fhs_reweighting_solve: null argument");
+  if (p->so > 0)
+    return fail(FHS_EUNSUPPORTED, "reweighting solve: overlapping spectral facets couple the sub-problems");
   if (prm->max_reweights < 0 || prm->min_iter < 0 || prm->max_iter < 1 || prm->max_iter < prm->min_iter)
     return fail(FHS_EINVAL, "reweighting solve: need max_reweights >= 0 and 1 <= max_iter, min_iter <= max_iter");
   if (!(prm->rw_tol >= 0) || !(prm->pdfb_tol >= 0) || !(prm->res_factor > 0))

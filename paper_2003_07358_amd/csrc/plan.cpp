@@ -36,7 +36,9 @@ namespace fhs {
 int64_t nuc_recon_lds(const fhs_plan *p, int S) {
   const int64_t W = p->lc16;
   if (p->C == 1) return (4 * static_cast<int64_t>(S) * p->L + 64) * 4;  // K held in registers
-  return static_cast<int64_t>(p->C) * W * (W + 1) * 8 + 5 * static_cast<int64_t>(S) * p->L * 4;
+  // K matrices, two staging buffers of X [S][L] and P [C][S][Ln], the output tile [C][S][Ln]
+  return static_cast<int64_t>(p->C) * W * (W + 1) * 8 +
+         static_cast<int64_t>(S) * (2 * p->L + 3 * static_cast<int64_t>(p->C) * p->Ln) * 4;
 }
 }  // namespace fhs
 
@@ -81,6 +83,15 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   if (c.precision != FHS_PRECISION_FP32 && c.precision != FHS_PRECISION_MIXED)
     return fail(FHS_EINVAL, "precision must be FHS_PRECISION_FP32 or FHS_PRECISION_MIXED");
   if (static_cast<int64_t>(c.ny) * c.nx * c.nchan > (int64_t(1) << 40)) return fail(FHS_EUNSUPPORTED, "cube too large");
+  if (c.spectral_overlap < 0) return fail(FHS_EINVAL, "negative spectral overlap");
+  if (c.spectral_overlap > 0) {
+    if (c.n_sub < 2) return fail(FHS_EINVAL, "spectral overlap needs at least two sub-cubes");
+    if (c.spectral_overlap > c.nchan / c.n_sub) return fail(FHS_EINVAL, "spectral overlap larger than a block");
+    if (c.nchan / c.n_sub + c.spectral_overlap > kMaxLc)
+      return fail(FHS_EUNSUPPORTED, "more than 64 channels per facet matrix");
+    if (c.precision != FHS_PRECISION_FP32)
+      return fail(FHS_EUNSUPPORTED, "spectral overlap is supported in the FP32 form only");
+  }
 
   fhs_plan *p = new (std::nothrow) fhs_plan();
   if (!p) return fail(FHS_ENOMEM, "out of host memory");
@@ -99,7 +110,9 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
 #endif
   if (FHS_DENSE_LANES && (p->Lc == 6 || p->Lc == 10 || p->Lc == 12 || p->Lc == 18 || p->Lc == 20)) lcp = p->Lc;
   p->Lcp = lcp;
-  p->lc16 = (p->Lc + 15) / 16 * 16;
+  p->so = c.spectral_overlap;
+  p->Ln = p->Lc + p->so;
+  p->lc16 = (p->Ln + 15) / 16 * 16;
 
   // tiles
   p->ty.resize(c.qy + 1);
@@ -137,7 +150,7 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
         f.wx1 = f.tx1;
         f.rows = static_cast<int64_t>(f.wy1 - f.wy0) * (f.wx1 - f.wx0);
         f.poff = poff;
-        poff += f.rows * p->Lc;
+        poff += f.rows * p->Ln;
         if (f.rows > p->max_rows) p->max_rows = static_cast<int>(f.rows);
         p->facets.push_back(f);
       }
@@ -266,7 +279,7 @@ int fhs_plan_create(const fhs_config *cfg, fhs_plan **out) {
   p->ws_kmat = ws;
   ws = align256(ws + nf * p->lc16 * p->lc16 * 8);
   p->ws_sig = ws;
-  ws = align256(ws + nf * p->Lc * 8);
+  ws = align256(ws + nf * p->Ln * 8);
   // closure sums: about 2048 blocks of whole pixel groups
   {
     const int64_t npix = static_cast<int64_t>(c.ny) * c.nx;
@@ -317,7 +330,7 @@ int fhs_plan_sizes(const fhs_plan *p, fhs_sizes *out) {
   out->n_w = p->I * p->L;
   out->n_theta = p->I * p->C;
   out->n_facets = static_cast<int64_t>(p->facets.size());
-  out->n_theta_bar = out->n_facets * p->Lc;
+  out->n_theta_bar = out->n_facets * p->Ln;
   out->n_bands = static_cast<int64_t>(p->bands.size());
   out->workspace_bytes = p->ws_bytes;
   return FHS_OK;
@@ -352,9 +365,12 @@ int fhs_plan_heuristics(const fhs_plan *p, const double *sigma_bar, double *mu, 
     mu[c] = sigma_bar[c] * (m + s);
   }
   for (size_t f = 0; f < p->facets.size(); ++f) {
+    // channels of the facet matrix: L_c, or with a spectral overlap the
+    // block's plus the o before it (none before the first block)
+    const int nc = p->so > 0 && p->facets[f].c > 0 ? p->Ln : p->Lc;
     const double n = static_cast<double>(p->facets[f].rows);
-    const double J = std::min(n, static_cast<double>(p->Lc));
-    mu_bar[f] = sigma_bar[p->facets[f].c] * std::sqrt(n * p->Lc / J);
+    const double J = std::min(n, static_cast<double>(nc));
+    mu_bar[f] = sigma_bar[p->facets[f].c] * std::sqrt(n * nc / J);
   }
   return FHS_OK;
 }

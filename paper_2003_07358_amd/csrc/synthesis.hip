@@ -328,7 +328,7 @@ syn_final_kernel(SynFinalArgs A) {
   const int c = grp % C, kq = grp / C < A.tk ? grp / C : 0;
   const bool lv = !idle && lane < Lc && grp / C < A.tk;
   const int p = c * Lc + lane;
-  const int ch = c + lane * C;
+  const int ch = A.contig ? p : c + lane * C;  // natural channel order of the image
   const int strip = blockIdx.x % A.strips, yb = blockIdx.x / A.strips;
   const int kx0 = A.x_begin / 2 + strip * A.tk;
   const int y0 = A.y_begin + yb * A.ty;
