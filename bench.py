@@ -71,13 +71,15 @@ def step_bytes(plan):
     return 4 * (s["n_x"] + 2 * s["n_p"] + 2 * s["n_w"] + s["n_theta"] + s["n_x"])
 
 
-def traffic_from_profiles(kernel, workload):
+def traffic_from_profiles(kernel, workload, precision):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel sources; else None."""
+    taken on the current kernel sources in the same precision form; else None."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
+    if d.get("precision", "fp32") != precision:
+        return None
     from paper_2003_07358_amd.profiling import source_hash
     files = d.get("sources")
     if d.get("source_hash") != source_hash(None if files in (None, "all") else files):
@@ -338,7 +340,7 @@ def main():
     frac = achieved / HBM_PEAK_GBS
     if not frac <= 1.0:
         raise SystemExit(f"roofline fraction {frac:.3f} > 1: the byte count or the launch timing is wrong")
-    traffic = traffic_from_profiles(args.kernel, w.name) if not plain else None
+    traffic = traffic_from_profiles(args.kernel, w.name, args.precision) if not plain else None
     sb = step_bytes(plan)
     log(f"[bench] {ms:.3f} ms/step (wall {wall / args.steps * 1e3:.3f}); {args.kernel}: "
         f"{kms / max(launches, 1):.3f} ms/launch ({launches} launches), {achieved:.0f} GB/s; step bytes "

@@ -9,6 +9,11 @@
         (FETCH_SIZE, WRITE_SIZE), each scaled by the reading of a reference
         copy kernel that moves a known number of bytes
 
+    python -m paper_2003_07358_amd.profiling step --fetch DIR --write DIR --marker REGEX
+            --library REGEX --calib REGEX --calib-bytes B --algorithmic B --name NAME --out FILE --command CMD
+        HBM bytes per step of every library kernel (and in total) from the same
+        two --pmc runs, the marker kernel counting the steps
+
     python -m paper_2003_07358_amd.profiling counters DIR [DIR ...] --kernel REGEX [--kernel REGEX ...]
             --out FILE --command CMD
         per-dispatch averages of every counter of one or more --pmc runs for
@@ -126,8 +131,9 @@ def cmd_stats(a):
 
 def cmd_traffic(a):
     files = KERNEL_SOURCES.get(a.sources) if a.sources else None
-    res = {"name": a.name, "sources": list(files) if files else "all", "source_hash": source_hash(files),
-           "command": a.command, "kernel_regex": a.kernel, "calib_regex": a.calib, "calib_bytes": a.calib_bytes}
+    res = {"name": a.name, "precision": a.precision, "sources": list(files) if files else "all",
+           "source_hash": source_hash(files), "command": a.command, "kernel_regex": a.kernel, "calib_regex": a.calib,
+           "calib_bytes": a.calib_bytes}
     total = 0.0
     for key, d, counter in (("fetch", a.fetch, "FETCH_SIZE"), ("write", a.write, "WRITE_SIZE")):
         agg = counter_per_dispatch(d, counter)
@@ -143,6 +149,44 @@ def cmd_traffic(a):
         res[f"{key}_bytes_per_launch"] = kib * 1024.0 * scale
         total += kib * 1024.0 * scale
     res["hbm_bytes_per_launch"] = total
+    with open(a.out, "w") as fh:
+        json.dump(res, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(res, indent=1))
+
+
+def cmd_step(a):
+    """HBM bytes of every library kernel of a run, per step: each kernel's
+    FETCH / WRITE sums (scaled by the reference copy kernel) divided by the
+    number of steps, counted as dispatches of the marker kernel (one per
+    step); beside the step's algorithmic bytes."""
+    res = {"name": a.name, "command": a.command, "algorithmic_bytes_per_step": a.algorithmic, "kernels": {}}
+    rx = re.compile(a.library)
+    steps = None
+    totals = {}
+    for key, d, counter in (("fetch", a.fetch, "FETCH_SIZE"), ("write", a.write, "WRITE_SIZE")):
+        agg = counter_per_dispatch(d, counter)
+        n = len(_matching(agg, a.marker))
+        steps = n if steps is None else steps
+        if n != steps:
+            raise ValueError("the two runs have different step counts")
+        scale = a.calib_bytes / (max(_matching(agg, a.calib)) * 1024.0)
+        tot = 0.0
+        for k, vs in agg.items():
+            if not rx.search(k):
+                continue
+            b = sum(vs) * 1024.0 * scale / n
+            res["kernels"].setdefault(k, {})[f"{key}_bytes_per_step"] = b
+            res["kernels"][k]["dispatches_per_step"] = len(vs) / n
+            tot += b
+        totals[key] = tot
+        res[f"{key}_scale"] = scale
+    res["steps_counted"] = steps
+    res["fetch_bytes_per_step"] = totals["fetch"]
+    res["write_bytes_per_step"] = totals["write"]
+    res["hbm_bytes_per_step"] = totals["fetch"] + totals["write"]
+    if a.algorithmic:
+        res["ratio_to_algorithmic"] = res["hbm_bytes_per_step"] / a.algorithmic
     with open(a.out, "w") as fh:
         json.dump(res, fh, indent=1)
         fh.write("\n")
@@ -185,13 +229,25 @@ def main(argv=None):
     t.add_argument("--out", required=True)
     t.add_argument("--command", default="")
     t.add_argument("--sources", default="", help="kernel whose source list the hash covers (default: all)")
+    t.add_argument("--precision", default="fp32", help="precision form of the profiled run")
+    st = sub.add_parser("step")
+    st.add_argument("--fetch", required=True)
+    st.add_argument("--write", required=True)
+    st.add_argument("--marker", required=True)
+    st.add_argument("--library", default="fhs::")
+    st.add_argument("--calib", required=True)
+    st.add_argument("--calib-bytes", type=float, required=True)
+    st.add_argument("--algorithmic", type=float, default=0.0)
+    st.add_argument("--name", required=True)
+    st.add_argument("--out", required=True)
+    st.add_argument("--command", default="")
     k = sub.add_parser("counters")
     k.add_argument("dirs", nargs="+")
     k.add_argument("--kernel", action="append", required=True)
     k.add_argument("--out", required=True)
     k.add_argument("--command", default="")
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "step": cmd_step, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":
