@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY.
 
 Per channel l of a cube of shape (ny, nx, L), with x_ref the ground truth and
-x the estimate (Sec. 4.2, reconstruction quality):
+x the estimate (Sec. 4.3, reconstruction quality):
 
 * SNR_l = 20 log10(||x_ref_l||_2 / ||x_ref_l - x_l||_2);
 * SNR_log_l: the same on the term-wise log10(z / eps_l + 1) of both images,

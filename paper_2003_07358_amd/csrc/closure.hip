@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(kThreads) closure_xi(ClosureArgs a) {
   }
 }
 
-// Reconstruction metrics (Sec. 4.2): per block and channel the four sums
+// Reconstruction metrics (Sec. 4.3): per block and channel the four sums
 // sum r^2, sum (r - x)^2 and, with noise levels, the same of
 // a = log10(r / eps + 1), b = log10(x / eps + 1); then one block sums the
 // partials in a fixed order and writes 10 log10(num / den) per channel.

@@ -256,7 +256,7 @@ def test_resume_from_checkpoint_is_bitwise(tmp_path):
 
 @pytest.mark.parametrize("L,with_log", [(20, True), (5, True), (64, False)])
 def test_snr_matches_oracle(L, with_log):
-    """Reconstruction SNR and log-scale SNR per channel (Sec. 4.2) against the
+    """Reconstruction SNR and log-scale SNR per channel (Sec. 4.3) against the
     oracle: the same float32 images, sums in float64 on both sides."""
     from oracle import metrics
     ny, nx = 37, 53

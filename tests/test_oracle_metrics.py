@@ -1,4 +1,4 @@
-"""Pins of the reconstruction metrics oracle (Sec. 4.2) against closed forms."""
+"""Pins of the reconstruction metrics oracle (Sec. 4.3) against closed forms."""
 import numpy as np
 import pytest
 
