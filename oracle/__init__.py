@@ -26,6 +26,10 @@ against the paper by eye:
                     100-channel case read literally: contiguous blocks whose
                     low-rankness facets overlap by a few channels with a
                     triangular spectral ramp; a reading, not in the paper).
+* ``nufft``      -- the measurement operator Phi = G F Z (Kaiser-Bessel
+                    de-gridding on a 2x oversampled grid) and the data-fidelity
+                    dual update with the preconditioned l2-ball projection by
+                    forward-backward sub-iterations (Sec. 2.1, Alg. 2, Sec. 3.2).
 * ``heuristics`` -- regularisation parameters (eqs. heuristic_fhs_sparsity and
                     heuristic_fhs_low_rank) and reweighting weights
                     (eqs. facet_hypersara_rank and facet_hypersara_sparsity).

@@ -172,3 +172,31 @@ def facet_selection(C, Q, prob, seed):
     """Random draw of the facets whose duals a randomized step updates:
     (C, Q) booleans, each true with probability prob."""
     return rng(seed).random((C, Q)) < prob
+
+
+def uv_coverage(M, seed, spread=0.35):
+    """A synthetic uv-coverage standing in for the VLA coverages of Sec. 4.1:
+    M points (omega_y, omega_x) in radians per pixel, radially concentrated
+    toward the origin like an interferometer's (Gaussian radii of scale
+    spread * pi, uniform angles), kept inside [-pi/2, pi/2)^2 so that the
+    coverage scaled by the channel's frequency ratio (up to about 1.8 over
+    the paper's bands) stays inside [-pi, pi)^2.  Includes conjugate-free
+    points only (no symmetry imposed)."""
+    r = rng(seed)
+    out = np.empty((0, 2))
+    while len(out) < M:
+        rad = np.abs(r.standard_normal(2 * M)) * spread * np.pi
+        ang = r.uniform(0, 2 * np.pi, 2 * M)
+        pts = np.stack([rad * np.sin(ang), rad * np.cos(ang)], axis=1)
+        pts = pts[np.all(np.abs(pts) < 0.5 * np.pi, axis=1)]
+        out = np.concatenate([out, pts])
+    return out[:M]
+
+
+def channel_coverages(M, L, seed):
+    """Per channel l, the reference coverage scaled by nu_l / nu_1 (Sec. 4.1:
+    the coverage of channel l is the reference one scaled by the frequency
+    ratio)."""
+    base = uv_coverage(M, seed)
+    nu = frequencies(L)
+    return [base * (nu[l] / nu[0]) for l in range(L)]
