@@ -446,6 +446,74 @@ int fhs_plan_profile(fhs_plan *plan, int32_t kernel_id, int32_t max_launches);
  * number of timed launches since the last read, and resets the counters. */
 int fhs_plan_profile_read(fhs_plan *plan, double *total_ms, int64_t *launches);
 
+/* ---------------------------------------------------------------- data fidelity
+ *
+ * The measurement operator of one channel, Phi_l = G_l F Z (Sec. 2.1, eq.
+ * model), for a real ny x nx image:
+ *   Z  zero-pads the image into a K1 x K2 grid (K = 2 N per axis), pixel n at
+ *      grid index (n - N/2) mod K (the image centred on the grid origin),
+ *      scaled by 1 / psi^(m / K) per axis (m = n - N/2), psi^ the continuous
+ *      Fourier transform of the interpolation kernel;
+ *   F  the unnormalised 2D DFT, exp(-2 pi i k.g / K);
+ *   G  de-gridding with the 7 x 7 Kaiser-Bessel kernel (Sec. 2.1, Sec. 4.1):
+ *      visibility j at the uv-point omega_j (radians per pixel; Phi x then
+ *      approximates sum_n x[n] exp(-i omega_j.(n - N/2))) at grid coordinate
+ *      t = omega K / (2 pi) sums the 7 x 7 grid points from ceil(t - 7/2),
+ *      weights psi(t - k) = I0(beta sqrt(1 - (2 (t - k) / 7)^2)) per axis,
+ *      beta = pi sqrt((7/2)^2 (3/2)^2 - 0.8) (Beatty, Nishimura and Pauly).
+ * One data block per channel.  FP32 storage and FFT, FP64 interpolation sums
+ * and reductions.  Visibilities are complex FP32 (re, im interleaved), all
+ * channels concatenated in channel order (channel l from sum_{l' < l} n_vis). */
+typedef struct fhs_data_plan fhs_data_plan;  /* opaque */
+
+typedef struct {
+  int32_t ny, nx;  /* image size: powers of two, 8 .. 4096                    */
+  int32_t nchan;   /* L                                                       */
+} fhs_data_config;
+
+/* n_vis: host [L] visibilities per channel; uv: host [sum n_vis][2]
+ * (omega_y, omega_x) per visibility, finite (any value; the grid wraps).
+ * Computes the interpolation tables, the scaling of Z and the inverse
+ * sampling density on the host.  FHS_EUNSUPPORTED for non-power-of-two
+ * sides or more than 2^31 visibilities. */
+int fhs_data_plan_create(const fhs_data_config *cfg, const int64_t *n_vis, const double *uv, fhs_data_plan **out);
+void fhs_data_plan_destroy(fhs_data_plan *plan);
+
+/* out[0] = total visibilities, out[1] = workspace bytes, out[2] = K1, out[3] = K2. */
+int fhs_data_plan_sizes(const fhs_data_plan *plan, int64_t out[4]);
+
+/* Caller-owned device workspace (256-byte aligned, at least out[1] bytes);
+ * the tables are copied into it now (host call, synchronises the device). */
+int fhs_data_plan_set_workspace(fhs_data_plan *plan, void *dev_ptr, int64_t bytes);
+
+/* The preconditioner of Sec. 3.2: U_j = 1 / (number of uv-points of channel l
+ * in the cell of the oversampled grid nearest to omega_j).  Host [sum n_vis]. */
+int fhs_data_preconditioner(const fhs_data_plan *plan, double *u_out);
+
+/* vis = Phi x for every channel.  x: device FP32 [ny][nx][L]; vis: device
+ * complex FP32 [sum n_vis]. */
+int fhs_nufft_forward(const fhs_data_plan *plan, const float *x, float *vis, void *stream);
+
+/* x = beta x + scale_l Re(Phi_l^dagger v) per channel (scale: device FP64 [L],
+ * or null for 1). */
+int fhs_nufft_adjoint(const fhs_data_plan *plan, const float *vis, float *x, const double *scale, float beta,
+                      void *stream);
+
+/* The data-fidelity dual update of Alg. 2 for every channel (one block each):
+ *   z  = U^-1 v + Phi xcheck   (the transform of the extrapolated iterate)
+ *   p  = projection of z onto B(y, eps_l) in the metric of U (eq.
+ *        prox_definition), by forward-backward sub-iterations (Sec. 3.2):
+ *        p = P_B(z), then n_sub times p <- P_B(p - gamma U (p - z)),
+ *        gamma = 1 / max_j U_j, P_B the Euclidean projection
+ *   v  <- U (z - p)
+ *   grad += eta_l Re(Phi^dagger v)   (the data part of the aggregation)
+ *   residual_l = ||y - Phi x||   (x the iterate; device FP64 [L], or null)
+ * xcheck, x, grad: device FP32 [ny][nx][L]; v (in / out), y: complex FP32
+ * [sum n_vis]; U: device FP32 [sum n_vis], > 0; eps, eta: device FP64 [L]. */
+int fhs_data_dual_update(const fhs_data_plan *plan, const float *xcheck, const float *x, float *v, const float *y,
+                         const float *U, const double *eps, const double *eta, int32_t n_sub, float *grad,
+                         double *residual, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -176,6 +176,8 @@ def project_ball_metric_fb(z, y, eps, U, n_sub):
     each sub-iteration p <- P_B(p - gamma U (p - z)) takes one Euclidean
     projection.  Starts from P_B(z); n_sub = 0 returns P_B(z)."""
     U = np.asarray(U, dtype=np.float64)
+    if U.size == 0:                      # an empty data block: nothing to project
+        return np.asarray(z).copy()
     gamma = 1.0 / np.max(U)
     p = project_ball(z, y, eps)
     for _ in range(n_sub):

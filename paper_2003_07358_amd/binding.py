@@ -24,6 +24,10 @@ class _Config(ctypes.Structure):
                  "spectral_overlap")]
 
 
+class _DataConfig(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("ny", "nx", "nchan")]
+
+
 class _Sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_x", "n_p", "n_coef", "n_w", "n_theta", "n_facets", "n_theta_bar", "n_bands",
@@ -113,6 +117,16 @@ SYMBOLS = {
     "fhs_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "fhs_plan_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
                                             ctypes.c_void_p]),
+    "fhs_data_plan_create": (ctypes.c_int, [ctypes.POINTER(_DataConfig), ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_void_p)]),
+    "fhs_data_plan_destroy": (None, [ctypes.c_void_p]),
+    "fhs_data_plan_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "fhs_data_plan_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "fhs_data_preconditioner": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fhs_nufft_forward": (ctypes.c_int, [ctypes.c_void_p] * 4),
+    "fhs_nufft_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_float, ctypes.c_void_p]),
+    "fhs_data_dual_update": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_int32] + [ctypes.c_void_p] * 3),
     "fhs_plan_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -522,3 +536,88 @@ class Graph:
 
     def __del__(self):
         self.close()
+
+
+class DataPlan:
+    """The measurement operator and the data dual update of one cube
+    (include/fhs.h, fhs_data_plan_create): image ny x nx x L, per channel l the
+    uv-points uv[l] (M_l x 2, radians per pixel)."""
+
+    def __init__(self, ny, nx, uv):
+        self._lib = lib()
+        self.L = len(uv)
+        self.ny, self.nx = ny, nx
+        self.n_vis = np.array([len(u) for u in uv], dtype=np.int64)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(u, dtype=np.float64).reshape(-1, 2) for u in uv]))
+        cfg = _DataConfig(ny, nx, self.L)
+        handle = ctypes.c_void_p()
+        _check(self._lib.fhs_data_plan_create(ctypes.byref(cfg), self.n_vis.ctypes.data_as(ctypes.c_void_p),
+                                              flat.ctypes.data_as(ctypes.c_void_p), ctypes.byref(handle)))
+        self._p = handle
+        out = (ctypes.c_int64 * 4)()
+        _check(self._lib.fhs_data_plan_sizes(self._p, out))
+        self.m, self.workspace_bytes, self.K1, self.K2 = list(out)
+        self.voff = np.concatenate([[0], np.cumsum(self.n_vis)])
+        self.workspace = None
+
+    def __del__(self):
+        p = getattr(self, "_p", None)
+        if p is not None and p.value:
+            self._lib.fhs_data_plan_destroy(p)
+            self._p = None
+
+    def attach_workspace(self, device="cuda"):
+        import torch
+        nbytes = max(256, self.workspace_bytes)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-ws.data_ptr()) % 256
+        self.workspace = ws
+        _check(self._lib.fhs_data_plan_set_workspace(self._p, ctypes.c_void_p(ws.data_ptr() + off), nbytes))
+        return self
+
+    def preconditioner(self):
+        """Inverse sampling density per visibility (host float64)."""
+        u = np.empty(self.m, dtype=np.float64)
+        _check(self._lib.fhs_data_preconditioner(self._p, u.ctypes.data_as(ctypes.c_void_p)))
+        return u
+
+    def _t(self, t, n, dtype, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise FhsError(f"{name}: expected a device tensor")
+        if t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+            raise FhsError(f"{name}: expected a contiguous {dtype} tensor of {n} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _need_ws(self):
+        if self.workspace is None:
+            raise FhsError("attach_workspace() first")
+
+    def forward(self, x, vis):
+        """vis (complex64, m) = Phi x (x float32 [ny][nx][L])."""
+        import torch
+        self._need_ws()
+        _check(self._lib.fhs_nufft_forward(self._p, self._t(x, self.ny * self.nx * self.L, torch.float32, "x"),
+                                           self._t(vis, self.m, torch.complex64, "vis"), _stream(x)))
+
+    def adjoint(self, vis, x, scale=None, beta=0.0):
+        """x = beta x + scale_l Re(Phi_l^dagger vis)."""
+        import torch
+        self._need_ws()
+        sc = self._t(scale, self.L, torch.float64, "scale") if scale is not None else None
+        _check(self._lib.fhs_nufft_adjoint(self._p, self._t(vis, self.m, torch.complex64, "vis"),
+                                           self._t(x, self.ny * self.nx * self.L, torch.float32, "x"), sc,
+                                           float(beta), _stream(x)))
+
+    def dual_update(self, xcheck, x, v, y, U, eps, eta, n_sub, grad, residual=None):
+        """fhs_data_dual_update (Alg. 2 data-fidelity lines)."""
+        import torch
+        self._need_ws()
+        n = self.ny * self.nx * self.L
+        res = self._t(residual, self.L, torch.float64, "residual") if residual is not None else None
+        _check(self._lib.fhs_data_dual_update(
+            self._p, self._t(xcheck, n, torch.float32, "xcheck"), self._t(x, n, torch.float32, "x"),
+            self._t(v, self.m, torch.complex64, "v"), self._t(y, self.m, torch.complex64, "y"),
+            self._t(U, self.m, torch.float32, "U"), self._t(eps, self.L, torch.float64, "eps"),
+            self._t(eta, self.L, torch.float64, "eta"), int(n_sub), self._t(grad, n, torch.float32, "grad"), res,
+            _stream(x)))

@@ -1,0 +1,327 @@
+// The measurement operator Phi = G F Z of one channel per image plane (Sec.
+// 2.1, eq. model) and the data-fidelity dual update of Alg. 2 (Sec. 3.2:
+// projection onto the l2 ball in the metric of a diagonal preconditioner by
+// forward-backward sub-iterations), for gfx950.
+//
+// Grid conventions: K = 2 N points per axis; the image is centred on the
+// grid origin (pixel n at index (n - N/2) mod K, times the scaling of Z);
+// F is the unnormalised DFT with exp(-2 pi i k g / K), its adjoint the
+// unnormalised inverse.  The forward path keeps the spectrum transposed
+// ([channel][k2][k1]) after its second FFT pass, and the de-gridding reads it
+// there; the adjoint path grids into that layout and transposes back.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "data_internal.h"
+#include "fhs_internal.h"
+
+namespace fhs {
+namespace data {
+
+namespace {
+
+__device__ __forceinline__ float2v cmul(float2v a, float2v b) {
+  return float2v{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// ---------------------------------------------------------------- Z and Z^T
+__global__ void __launch_bounds__(256) pad_kernel(PadArgs a) {
+  const int64_t n = static_cast<int64_t>(a.L) * a.K1 * a.K2;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int k2 = static_cast<int>(i % a.K2);
+    const int64_t r = i / a.K2;
+    const int k1 = static_cast<int>(r % a.K1);
+    const int l = static_cast<int>(r / a.K1);
+    const int n1 = (k1 < a.K1 / 2 ? k1 : k1 - a.K1) + a.ny / 2;
+    const int n2 = (k2 < a.K2 / 2 ? k2 : k2 - a.K2) + a.nx / 2;
+    float v = 0.0f;
+    if (n1 >= 0 && n1 < a.ny && n2 >= 0 && n2 < a.nx)
+      v = a.x[(static_cast<int64_t>(n1) * a.nx + n2) * a.L + l] * (a.s1[n1] * a.s2[n2]);
+    a.grid[i] = float2v{v, 0.0f};
+  }
+}
+
+__global__ void __launch_bounds__(256) crop_kernel(CropArgs a) {
+  const int64_t n = static_cast<int64_t>(a.ny) * a.nx * a.L;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int l = static_cast<int>(i % a.L);
+    const int64_t pix = i / a.L;
+    const int n2 = static_cast<int>(pix % a.nx), n1 = static_cast<int>(pix / a.nx);
+    int k1 = n1 - a.ny / 2, k2 = n2 - a.nx / 2;
+    if (k1 < 0) k1 += a.K1;
+    if (k2 < 0) k2 += a.K2;
+    const float g = a.grid[(static_cast<int64_t>(l) * a.K1 + k1) * a.K2 + k2].x * (a.s1[n1] * a.s2[n2]);
+    const float sc = a.scale ? static_cast<float>(a.scale[l]) : 1.0f;
+    a.x[i] = a.beta != 0.0f ? fmaf(a.beta, a.x[i], sc * g) : sc * g;
+  }
+}
+
+// ---------------------------------------------------------------- F, by rows
+// One workgroup per row of K points (a power of two): the row is copied into
+// LDS and transformed by log2(K) radix-2 Stockham passes (self-sorting, so no
+// bit reversal); pass m (m = K/2, K/4, ..., 1; stride s = K / (2 m)) maps
+// butterfly b = p s + q to
+//   y[q + s 2p] = x[q + s p] + x[q + s (p + m)]
+//   y[q + s (2p + 1)] = (x[q + s p] - x[q + s (p + m)]) W^(p s)
+// with W = exp(sign 2 pi i / K), read from the table of exp(-2 pi i k / K).
+__global__ void __launch_bounds__(1024) fft_rows_kernel(float2v *data, int K, const float2v *tw, int sign) {
+  extern __shared__ float2v buf[];
+  float2v *x = buf, *y = buf + K;
+  float2v *row = data + static_cast<int64_t>(blockIdx.x) * K;
+  for (int i = threadIdx.x; i < K; i += blockDim.x) x[i] = row[i];
+  __syncthreads();
+  for (int m = K / 2, s = 1; m >= 1; m >>= 1, s <<= 1) {
+    for (int b = threadIdx.x; b < K / 2; b += blockDim.x) {
+      const int p = b / s, q = b - p * s;
+      float2v w = tw[p * s];
+      if (sign > 0) w.y = -w.y;
+      const float2v u = x[q + s * p], v = x[q + s * (p + m)];
+      y[q + s * 2 * p] = float2v{u.x + v.x, u.y + v.y};
+      y[q + s * (2 * p + 1)] = cmul(float2v{u.x - v.x, u.y - v.y}, w);
+    }
+    __syncthreads();
+    float2v *t = x;
+    x = y;
+    y = t;
+  }
+  for (int i = threadIdx.x; i < K; i += blockDim.x) row[i] = x[i];
+}
+
+// out plane [Cc][R] = transpose of in plane [R][Cc], through 32 x 32 LDS tiles
+__global__ void __launch_bounds__(256) transpose_kernel(const float2v *in, float2v *out, int R, int Cc) {
+  __shared__ float2v tile[32][33];
+  const int64_t plane = static_cast<int64_t>(blockIdx.z) * R * Cc;
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows per pass
+  for (int j = ty; j < 32; j += 8) {
+    const int r = r0 + j, c = c0 + tx;
+    if (r < R && c < Cc) tile[j][tx] = in[plane + static_cast<int64_t>(r) * Cc + c];
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int c = c0 + j, r = r0 + tx;
+    if (r < R && c < Cc) out[plane + static_cast<int64_t>(c) * R + r] = tile[tx][j];
+  }
+}
+
+__global__ void __launch_bounds__(256) fill_zero_kernel(float2v *d, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    d[i] = float2v{0.0f, 0.0f};
+}
+
+// ---------------------------------------------------------------- G and G^H
+// One thread per visibility: the J x J grid points from its first indices,
+// wrapped modulo K, weights psi(t1 - k1) psi(t2 - k2) (FP64 accumulation).
+__global__ void __launch_bounds__(256) degrid_kernel(InterpArgs a) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= a.m) return;
+  const VisInfo vi = a.info[j];
+  const float *w = a.w + j * 2 * kKbWidth;
+  const float2v *plane = a.spec + static_cast<int64_t>(vi.chan) * a.K1 * a.K2;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < kKbWidth; ++b) {
+    int k2 = vi.k2 + b;
+    if (k2 >= a.K2) k2 -= a.K2;
+    const float2v *rowp = plane + static_cast<int64_t>(k2) * a.K1;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int c = 0; c < kKbWidth; ++c) {
+      int k1 = vi.k1 + c;
+      if (k1 >= a.K1) k1 -= a.K1;
+      const float2v g = rowp[k1];
+      sr += static_cast<double>(w[c]) * g.x;
+      si += static_cast<double>(w[c]) * g.y;
+    }
+    re += static_cast<double>(w[kKbWidth + b]) * sr;
+    im += static_cast<double>(w[kKbWidth + b]) * si;
+  }
+  a.vis_out[j] = float2v{static_cast<float>(re), static_cast<float>(im)};
+}
+
+__global__ void __launch_bounds__(256) grid_kernel(InterpArgs a) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= a.m) return;
+  const VisInfo vi = a.info[j];
+  const float *w = a.w + j * 2 * kKbWidth;
+  const float2v v = a.vis_in[j];
+  float2v *plane = a.grid + static_cast<int64_t>(vi.chan) * a.K1 * a.K2;
+  for (int b = 0; b < kKbWidth; ++b) {
+    int k2 = vi.k2 + b;
+    if (k2 >= a.K2) k2 -= a.K2;
+    float2v *rowp = plane + static_cast<int64_t>(k2) * a.K1;
+    const float wb = w[kKbWidth + b];
+    for (int c = 0; c < kKbWidth; ++c) {
+      int k1 = vi.k1 + c;
+      if (k1 >= a.K1) k1 -= a.K1;
+      const float ww = wb * w[c];
+      atomicAdd(&rowp[k1].x, ww * v.x);
+      atomicAdd(&rowp[k1].y, ww * v.y);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- data dual
+// Fixed-order workgroup sum (each thread's partial, then a tree in LDS).
+__device__ double block_sum(double v, double *red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_max(double v, double *red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// One workgroup per channel (one data block each).  z = v / U + Phi xcheck;
+// p = P_B(z), then n_sub sub-iterations p <- P_B(p - gamma U (p - z)) with
+// gamma = 1 / max U (P_B the Euclidean projection onto B(y, eps)); v <- U (z - p);
+// residual ||y - Phi x||.  z is recomputed from v, U and Phi xcheck wherever it
+// is needed (v changes only in the last pass).
+__global__ void __launch_bounds__(kDualThreads) data_dual_kernel(DualArgs a) {
+  __shared__ double red[kDualThreads];
+  const int l = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+  const int64_t j0 = a.voff[l], j1 = a.voff[l + 1];
+  auto zval = [&](int64_t j) {
+    const float2v v = a.v[j], c = a.yc[j];
+    const float u = a.U[j];
+    return float2v{v.x / u + c.x, v.y / u + c.y};
+  };
+  double umax = 0.0, d2 = 0.0, r2 = 0.0;
+  for (int64_t j = j0 + t; j < j1; j += nt) {
+    const float2v z = zval(j), y = a.y[j], yx = a.yx[j];
+    umax = fmax(umax, static_cast<double>(a.U[j]));
+    const double dx = static_cast<double>(z.x) - y.x, dy = static_cast<double>(z.y) - y.y;
+    d2 += dx * dx + dy * dy;
+    const double ex = static_cast<double>(y.x) - yx.x, ey = static_cast<double>(y.y) - yx.y;
+    r2 += ex * ex + ey * ey;
+  }
+  umax = block_max(umax, red);
+  d2 = block_sum(d2, red);
+  r2 = block_sum(r2, red);
+  const double eps = a.eps[l];
+  // p = P_B(z)
+  double f = d2 > eps * eps ? eps / sqrt(d2) : 1.0;
+  for (int64_t j = j0 + t; j < j1; j += nt) {
+    const float2v z = zval(j), y = a.y[j];
+    a.p[j] = float2v{static_cast<float>(y.x + f * (static_cast<double>(z.x) - y.x)),
+                     static_cast<float>(y.y + f * (static_cast<double>(z.y) - y.y))};
+  }
+  const float gamma = umax > 0.0 ? static_cast<float>(1.0 / umax) : 0.0f;
+  for (int s = 0; s < a.n_sub; ++s) {
+    // q = p - gamma U (p - z), stored in p; then p = P_B(q)
+    double q2 = 0.0;
+    for (int64_t j = j0 + t; j < j1; j += nt) {
+      const float2v z = zval(j), y = a.y[j], p = a.p[j];
+      const float g = gamma * a.U[j];
+      const float2v q{p.x - g * (p.x - z.x), p.y - g * (p.y - z.y)};
+      a.p[j] = q;
+      const double dx = static_cast<double>(q.x) - y.x, dy = static_cast<double>(q.y) - y.y;
+      q2 += dx * dx + dy * dy;
+    }
+    q2 = block_sum(q2, red);
+    f = q2 > eps * eps ? eps / sqrt(q2) : 1.0;
+    for (int64_t j = j0 + t; j < j1; j += nt) {
+      const float2v q = a.p[j], y = a.y[j];
+      a.p[j] = float2v{static_cast<float>(y.x + f * (static_cast<double>(q.x) - y.x)),
+                       static_cast<float>(y.y + f * (static_cast<double>(q.y) - y.y))};
+    }
+    __syncthreads();
+  }
+  // v <- U (z - p)
+  for (int64_t j = j0 + t; j < j1; j += nt) {
+    const float2v z = zval(j), p = a.p[j];
+    const float u = a.U[j];
+    a.v[j] = float2v{u * (z.x - p.x), u * (z.y - p.y)};
+  }
+  if (t == 0 && a.residual) a.residual[l] = sqrt(r2);
+}
+
+int check(const char *what) {
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(FHS_EHIP, std::string(what) + ": " + hipGetErrorString(err));
+  return FHS_OK;
+}
+
+unsigned grid_for(int64_t n, int threads) {
+  const int64_t g = (n + threads - 1) / threads;
+  return static_cast<unsigned>(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+
+}  // namespace
+
+int launch_pad(const PadArgs &a, void *stream) {
+  const int64_t n = static_cast<int64_t>(a.L) * a.K1 * a.K2;
+  hipLaunchKernelGGL(pad_kernel, dim3(grid_for(n, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), a);
+  return check("nufft pad");
+}
+
+int launch_crop(const CropArgs &a, void *stream) {
+  const int64_t n = static_cast<int64_t>(a.ny) * a.nx * a.L;
+  hipLaunchKernelGGL(crop_kernel, dim3(grid_for(n, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), a);
+  return check("nufft crop");
+}
+
+int launch_fft_rows(float2v *data, int64_t rows, int K, const float2v *tw, int sign, void *stream) {
+  if (rows <= 0) return FHS_OK;
+  if (K < 2 || K > kMaxGrid || (K & (K - 1)) != 0) return fail(FHS_EUNSUPPORTED, "FFT length must be a power of two");
+  if (rows > 0x7fffffff) return fail(FHS_EUNSUPPORTED, "too many FFT rows");
+  const int threads = K / 2 < 1024 ? (K / 2 < 64 ? 64 : K / 2) : 1024;
+  const size_t lds = static_cast<size_t>(2 * K) * sizeof(float2v);
+  hipLaunchKernelGGL(fft_rows_kernel, dim3(static_cast<unsigned>(rows)), dim3(threads), lds,
+                     static_cast<hipStream_t>(stream), data, K, tw, sign);
+  return check("nufft fft rows");
+}
+
+int launch_transpose(const float2v *in, float2v *out, int R, int Cc, int planes, void *stream) {
+  const dim3 grid((Cc + 31) / 32, (R + 31) / 32, planes);
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), in, out, R, Cc);
+  return check("nufft transpose");
+}
+
+int launch_fill_zero(float2v *data, int64_t n, void *stream) {
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), data,
+                     n);
+  return check("nufft fill");
+}
+
+int launch_degrid(const InterpArgs &a, void *stream) {
+  if (a.m <= 0) return FHS_OK;
+  hipLaunchKernelGGL(degrid_kernel, dim3(static_cast<unsigned>((a.m + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), a);
+  return check("nufft degrid");
+}
+
+int launch_grid(const InterpArgs &a, void *stream) {
+  if (a.m <= 0) return FHS_OK;
+  hipLaunchKernelGGL(grid_kernel, dim3(static_cast<unsigned>((a.m + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), a);
+  return check("nufft grid");
+}
+
+int launch_data_dual(const DualArgs &a, int L, void *stream) {
+  hipLaunchKernelGGL(data_dual_kernel, dim3(L), dim3(kDualThreads), 0, static_cast<hipStream_t>(stream), a);
+  return check("data dual update");
+}
+
+}  // namespace data
+}  // namespace fhs

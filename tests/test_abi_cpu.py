@@ -25,7 +25,7 @@ def declared_symbols():
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(fhs.library_path())
     names = declared_symbols()
-    assert len(names) == 34
+    assert len(names) == 42
     for n in names:
         assert hasattr(lib, n), n
     # and the binding declares a signature for each of them
@@ -126,3 +126,23 @@ def test_tuning_roundtrip_and_validation():
         with pytest.raises(fhs.FhsError):
             plan.tuning = bad
     assert plan.tuning == t2   # a rejected setting leaves the plan unchanged
+
+
+def test_data_plan_host_side_matches_oracle():
+    """The data plan's host computations (no GPU): grid sizes and the inverse
+    sampling density per channel against the oracle's."""
+    import synth
+    from oracle import nufft
+    covs = synth.channel_coverages(700, 3, 11)
+    covs[1] = covs[1][:0]                      # a channel without visibilities
+    dp = fhs.DataPlan(32, 64, covs)
+    assert (dp.K1, dp.K2, dp.m) == (64, 128, 1400)
+    u = dp.preconditioner()
+    for l, c in enumerate(covs):
+        if len(c):
+            ref = nufft.inverse_density(c, 64, 128)
+            assert np.array_equal(u[dp.voff[l]:dp.voff[l + 1]], ref)
+    with pytest.raises(fhs.FhsError):
+        fhs.DataPlan(48, 64, covs)             # not a power of two
+    with pytest.raises(fhs.FhsError):
+        fhs.DataPlan(32, 64, [np.array([[np.nan, 0.0]])])
