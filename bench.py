@@ -215,11 +215,19 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (the reference "
                          "dispatch that scales HBM counters read under rocprofv3 --pmc)")
+    ap.add_argument("--data-block", action="store_true",
+                    help="time the data-fidelity dual update (measurement operator, preconditioned l2-ball "
+                         "projection) on a 1024x2048x20 cube instead of the facet step")
+    ap.add_argument("--vis-per-channel", type=int, default=1 << 20)
+    ap.add_argument("--n-sub", type=int, default=10, help="forward-backward sub-iterations of the projection")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of the "
               "facet step is a design, not a measured path", file=sys.stderr)
         sys.exit(2)
+
+    if args.data_block:
+        return data_block_bench(args)
 
     import synth
     w = synth.WORKLOADS[args.workload]
@@ -376,6 +384,72 @@ def main():
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+
+
+def data_block_bench(args):
+    """One fhs_data_dual_update per step (Alg. 2 data-fidelity lines: two
+    forward NUFFTs, the preconditioned projection by sub-iterations, the
+    adjoint into the gradient) on the 1024 x 2048 x 20 cube with a synthetic
+    coverage of vis_per_channel points per channel, scaled by the frequency
+    ratio.  Prints one JSON line (visibilities per second)."""
+    import torch
+
+    import paper_2003_07358_amd as fhs
+    import synth
+    w = synth.WORKLOADS["cfg2_1024x2048x20"]
+    X = synth.workload_cube(w)
+    L, M = w.L, args.vis_per_channel
+    log(f"[bench] data block: {w.ny}x{w.nx}x{L}, {M} visibilities per channel, {args.n_sub} sub-iterations")
+    covs = synth.channel_coverages(M, L, synth.BASE_SEED + 77)
+    dp = fhs.DataPlan(w.ny, w.nx, covs).attach_workspace()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    x = dev(X)
+    U = dev(dp.preconditioner().astype(np.float32))
+    y = torch.empty(dp.m, dtype=torch.complex64, device="cuda")
+    dp.forward(x, y)                                   # data: the cube's visibilities (plus a stand-in noise)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    y += 0.01 * torch.randn(dp.m, dtype=torch.complex64, device="cuda", generator=g) * y.abs().mean()
+    xc = x * 1.01
+    v = torch.zeros(dp.m, dtype=torch.complex64, device="cuda")
+    grad = torch.zeros_like(x)
+    eps = torch.full((L,), 0.5, dtype=torch.float64, device="cuda") * torch.tensor(
+        [float(torch.linalg.vector_norm(y[dp.voff[l]:dp.voff[l + 1]])) for l in range(L)], dtype=torch.float64,
+        device="cuda") * 0.01
+    eta = torch.ones(L, dtype=torch.float64, device="cuda")
+    res = torch.zeros(L, dtype=torch.float64, device="cuda")
+
+    def one():
+        dp.dual_update(xc, x, v, y, U, eps, eta, args.n_sub, grad, res)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        one()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    N = w.ny * w.nx
+    # algorithmic bytes of one call: the images read (xcheck, x) and the
+    # gradient read and written, the visibilities (y, U read; v read and
+    # written), and for each of the three 2D FFTs of the 2x2-oversampled grid
+    # one read and one write of it
+    algo = 4 * N * L * 4 + dp.m * (8 + 4 + 16) + 3 * 2 * (8 * 4 * N * L)
+    achieved = algo / (ms / 1e3) / 1e9
+    line = {"metric": "data-fidelity dual update (Alg. 2 data-fidelity lines) visibilities/s", "value": dp.m / (ms / 1e3),
+            "unit": "visibilities/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 (FFT), f64 (sums)",
+            "data": "synthetic (seeded blob cube, Gaussian-radius uv-coverage scaled per channel)",
+            "config": {"workload": f"data_{w.ny}x{w.nx}x{L}_m{M}", "ny": w.ny, "nx": w.nx, "channels": L,
+                       "visibilities": int(dp.m), "grid": [int(dp.K1), int(dp.K2)], "kernel": "Kaiser-Bessel 7x7",
+                       "sub_iterations": args.n_sub},
+            "roofline": {"kernel": "whole call", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "bytes_per_call": algo}}
+    log(f"[bench] data block: {ms:.3f} ms per call, {dp.m / (ms / 1e3) / 1e9:.2f} G visibilities/s")
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -72,6 +72,7 @@ def _db(d):
 
 def short_name(name):
     """Kernel name without the argument list (template arguments kept)."""
+    name = name.replace("(anonymous namespace)::", "")
     depth = 0
     for i, ch in enumerate(name):
         if ch == "<":
