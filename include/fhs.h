@@ -472,7 +472,7 @@ typedef struct {
 } fhs_data_config;
 
 /* n_vis: host [L] visibilities per channel; uv: host [sum n_vis][2]
- * (omega_y, omega_x) per visibility, finite (any value; the grid wraps).
+ * (omega_y, omega_x) per visibility, |omega| < 1e6 (the grid wraps).
  * Computes the interpolation tables, the scaling of Z and the inverse
  * sampling density on the host.  FHS_EUNSUPPORTED for non-power-of-two
  * sides or more than 2^31 visibilities. */

@@ -96,6 +96,9 @@ int adjoint(const fhs_data_plan *p, const float2v *vis, float *x, const double *
   ia.vis_in = vis;
   ia.info = wsp<VisInfo>(p, p->off_info);
   ia.w = wsp<float>(p, p->off_w);
+  ia.perm = wsp<int32_t>(p, p->off_perm);
+  ia.items = wsp<GridItem>(p, p->off_items);
+  ia.n_items = static_cast<int64_t>(p->items.size());
   ia.m = p->m;
   ia.K1 = p->K1;
   ia.K2 = p->K2;
@@ -169,9 +172,9 @@ int fhs_data_plan_create(const fhs_data_config *cfg, const int64_t *n_vis, const
   for (int l = 0; l < p->L; ++l)
     for (int64_t j = p->voff[l]; j < p->voff[l + 1]; ++j) {
       const double w1 = uv[2 * j], w2 = uv[2 * j + 1];
-      if (!std::isfinite(w1) || !std::isfinite(w2)) {
+      if (!(std::fabs(w1) < 1e6) || !(std::fabs(w2) < 1e6)) {
         delete p;
-        return fail(FHS_EINVAL, "uv-points must be finite");
+        return fail(FHS_EINVAL, "uv-points must be finite, below 1e6 radians per pixel in magnitude");
       }
       const double t1 = w1 * p->K1 / (2.0 * kPi), t2 = w2 * p->K2 / (2.0 * kPi);
       const int64_t k1 = static_cast<int64_t>(std::ceil(t1 - kKbWidth / 2.0));
@@ -193,6 +196,34 @@ int fhs_data_plan_create(const fhs_data_config *cfg, const int64_t *n_vis, const
       ++counts[cell[j]];
     }
   for (int64_t j = 0; j < p->m; ++j) p->density_inv[j] = 1.0 / static_cast<double>(counts[cell[j]]);
+  // gridding order: visibilities sorted by (channel, tile of their first grid
+  // indices), each run of one tile cut into work items of at most kGridChunk
+  {
+    const int64_t n2 = (p->K2 + kGridTile - 1) / kGridTile, n1 = (p->K1 + kGridTile - 1) / kGridTile;
+    auto key = [&](int64_t j) {
+      const VisInfo &v = p->info[j];
+      return (static_cast<int64_t>(v.chan) * n1 + v.k1 / kGridTile) * n2 + v.k2 / kGridTile;
+    };
+    p->perm.resize(p->m);
+    for (int64_t j = 0; j < p->m; ++j) p->perm[j] = static_cast<int32_t>(j);
+    std::stable_sort(p->perm.begin(), p->perm.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
+    for (int64_t i = 0; i < p->m;) {
+      const int64_t k = key(p->perm[i]);
+      int64_t e = i;
+      while (e < p->m && key(p->perm[e]) == k) ++e;
+      for (int64_t s0 = i; s0 < e; s0 += kGridChunk) {
+        const VisInfo &v = p->info[p->perm[s0]];
+        GridItem it{};
+        it.chan = v.chan;
+        it.t1 = v.k1 / kGridTile;
+        it.t2 = v.k2 / kGridTile;
+        it.start = static_cast<int32_t>(s0);
+        it.count = static_cast<int32_t>(std::min<int64_t>(kGridChunk, e - s0));
+        p->items.push_back(it);
+      }
+      i = e;
+    }
+  }
   // workspace: two grids, three visibility buffers, the tables
   const int64_t g = static_cast<int64_t>(p->L) * p->K1 * p->K2 * sizeof(float2v);
   const int64_t vb = std::max<int64_t>(p->m, 1) * sizeof(float2v);
@@ -221,6 +252,14 @@ int fhs_data_plan_create(const fhs_data_config *cfg, const int64_t *n_vis, const
   ws = align256(ws + (p->K2 / 2) * sizeof(float2v));
   p->off_voff = ws;
   ws = align256(ws + (p->L + 1) * sizeof(int64_t));
+  p->off_perm = ws;
+  ws = align256(ws + std::max<int64_t>(p->m, 1) * sizeof(int32_t));
+  p->off_items = ws;
+  ws = align256(ws + std::max<int64_t>(static_cast<int64_t>(p->items.size()), 1) * sizeof(GridItem));
+  p->off_part = ws;
+  ws = align256(ws + static_cast<int64_t>(p->L) * kDualBlocks * 4 * sizeof(double));
+  p->off_chs = ws;
+  ws = align256(ws + static_cast<int64_t>(p->L) * 4 * sizeof(double));
   p->ws_bytes = ws;
   *out = p;
   return FHS_OK;
@@ -252,6 +291,8 @@ int fhs_data_plan_set_workspace(fhs_data_plan *p, void *dev_ptr, int64_t bytes) 
                   up(p->off_tw1, p->tw1.data(), p->tw1.size() * sizeof(float2v)) &&
                   up(p->off_tw2, p->tw2.data(), p->tw2.size() * sizeof(float2v)) &&
                   up(p->off_voff, p->voff.data(), p->voff.size() * sizeof(int64_t)) &&
+                  up(p->off_perm, p->perm.data(), p->perm.size() * sizeof(int32_t)) &&
+                  up(p->off_items, p->items.data(), p->items.size() * sizeof(GridItem)) &&
                   hipDeviceSynchronize() == hipSuccess;
   if (!ok) return fail(FHS_EHIP, "fhs_data_plan_set_workspace: copying the tables failed");
   p->ws = dev_ptr;
@@ -297,8 +338,11 @@ int fhs_data_dual_update(const fhs_data_plan *p, const float *xcheck, const floa
   d.eps = eps;
   d.voff = wsp<int64_t>(p, p->off_voff);
   d.residual = residual;
+  d.part = wsp<double>(p, p->off_part);
+  d.chs = wsp<double>(p, p->off_chs);
   d.n_sub = n_sub;
-  if (int rc = launch_data_dual(d, p->L, stream)) return rc;
+  d.L = p->L;
+  if (int rc = launch_data_dual(d, stream)) return rc;
   return adjoint(p, reinterpret_cast<const float2v *>(v), grad, eta, 1.0f, stream);
 }
 

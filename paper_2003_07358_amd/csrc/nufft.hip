@@ -142,30 +142,57 @@ __global__ void __launch_bounds__(256) degrid_kernel(InterpArgs a) {
   a.vis_out[j] = float2v{static_cast<float>(re), static_cast<float>(im)};
 }
 
+// Gridding (G^H) by work items: the visibilities of one channel whose first
+// grid indices lie in one tile of kGridTile x kGridTile points (sorted on the
+// host) accumulate into the tile and its 6-point halo in LDS (LDS atomics),
+// which is then added to the grid (one global atomic per touched point and
+// item instead of 49 per visibility: the coverage concentrates many
+// visibilities on few grid points).
+constexpr int kTileExt = kGridTile + kKbWidth - 1;
+
 __global__ void __launch_bounds__(256) grid_kernel(InterpArgs a) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= a.m) return;
-  const VisInfo vi = a.info[j];
-  const float *w = a.w + j * 2 * kKbWidth;
-  const float2v v = a.vis_in[j];
-  float2v *plane = a.grid + static_cast<int64_t>(vi.chan) * a.K1 * a.K2;
-  for (int b = 0; b < kKbWidth; ++b) {
-    int k2 = vi.k2 + b;
-    if (k2 >= a.K2) k2 -= a.K2;
-    float2v *rowp = plane + static_cast<int64_t>(k2) * a.K1;
-    const float wb = w[kKbWidth + b];
-    for (int c = 0; c < kKbWidth; ++c) {
-      int k1 = vi.k1 + c;
-      if (k1 >= a.K1) k1 -= a.K1;
-      const float ww = wb * w[c];
-      atomicAdd(&rowp[k1].x, ww * v.x);
-      atomicAdd(&rowp[k1].y, ww * v.y);
+  __shared__ float tre[kTileExt * kTileExt], tim[kTileExt * kTileExt];
+  const GridItem it = a.items[blockIdx.x];
+  for (int e = threadIdx.x; e < kTileExt * kTileExt; e += blockDim.x) tre[e] = tim[e] = 0.0f;
+  __syncthreads();
+  for (int i = it.start + threadIdx.x; i < it.start + it.count; i += blockDim.x) {
+    const int64_t j = a.perm[i];
+    const VisInfo vi = a.info[j];
+    const float *w = a.w + j * 2 * kKbWidth;
+    const float2v v = a.vis_in[j];
+    const int r0 = vi.k1 - it.t1 * kGridTile, c0 = vi.k2 - it.t2 * kGridTile;  // in [0, kGridTile)
+    for (int b = 0; b < kKbWidth; ++b) {
+      const float wb = w[kKbWidth + b];
+      for (int c = 0; c < kKbWidth; ++c) {
+        const float ww = wb * w[c];
+        const int e = (c0 + b) * kTileExt + r0 + c;
+        atomicAdd(&tre[e], ww * v.x);
+        atomicAdd(&tim[e], ww * v.y);
+      }
     }
+  }
+  __syncthreads();
+  float2v *plane = a.grid + static_cast<int64_t>(it.chan) * a.K1 * a.K2;
+  for (int e = threadIdx.x; e < kTileExt * kTileExt; e += blockDim.x) {
+    const float re = tre[e], im = tim[e];
+    if (re == 0.0f && im == 0.0f) continue;
+    const int cb = e / kTileExt, ra = e - cb * kTileExt;
+    const int g2 = (it.t2 * kGridTile + cb) % a.K2, g1 = (it.t1 * kGridTile + ra) % a.K1;
+    atomicAdd(&plane[static_cast<int64_t>(g2) * a.K1 + g1].x, re);
+    atomicAdd(&plane[static_cast<int64_t>(g2) * a.K1 + g1].y, im);
   }
 }
 
 // ---------------------------------------------------------------- data dual
-// Fixed-order workgroup sum (each thread's partial, then a tree in LDS).
+// The update of one channel (one data block) in passes over its visibilities,
+// kDualBlocks workgroups per channel, each writing its partial sums (FP64, a
+// fixed-order tree in LDS), then one workgroup per channel summing them in
+// order:
+//   pass 0: d2 = ||z - y||^2, r2 = ||y - Phi x||^2, max U   (z = v / U + Phi xcheck)
+//           -> f = min(1, eps / sqrt(d2)) (p = P_B(z) = y + f (z - y)), gamma = 1 / max U
+//   pass s = 1 .. n_sub: p = y + f (prev - y) (prev = z, then the stored q);
+//           q = p - gamma U (p - z), stored; ||q - y||^2 -> f
+//   last pass: p = y + f (prev - y); v <- U (z - p)
 __device__ double block_sum(double v, double *red) {
   const int t = threadIdx.x;
   red[t] = v;
@@ -192,68 +219,78 @@ __device__ double block_max(double v, double *red) {
   return r;
 }
 
-// One workgroup per channel (one data block each).  z = v / U + Phi xcheck;
-// p = P_B(z), then n_sub sub-iterations p <- P_B(p - gamma U (p - z)) with
-// gamma = 1 / max U (P_B the Euclidean projection onto B(y, eps)); v <- U (z - p);
-// residual ||y - Phi x||.  z is recomputed from v, U and Phi xcheck wherever it
-// is needed (v changes only in the last pass).
-__global__ void __launch_bounds__(kDualThreads) data_dual_kernel(DualArgs a) {
+__device__ __forceinline__ float2v zval(const DualArgs &a, int64_t j) {
+  const float2v v = a.v[j], c = a.yc[j];
+  const float u = a.U[j];
+  return float2v{v.x / u + c.x, v.y / u + c.y};
+}
+
+// mode 0: first pass; 1: a sub-iteration (first = 1 when prev is z); 2: the last pass
+__global__ void __launch_bounds__(kDualThreads) dual_pass_kernel(DualArgs a, int mode, int first) {
   __shared__ double red[kDualThreads];
-  const int l = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
-  const int64_t j0 = a.voff[l], j1 = a.voff[l + 1];
-  auto zval = [&](int64_t j) {
-    const float2v v = a.v[j], c = a.yc[j];
+  const int l = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
+  const int64_t c0 = a.voff[l], n = a.voff[l + 1] - c0;
+  const int64_t len = (n + kDualBlocks - 1) / kDualBlocks;
+  const int64_t j0 = c0 + blk * len, j1 = c0 + min(n, (blk + 1) * len);
+  const double f = a.chs[4 * l], gamma = a.chs[4 * l + 1];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int64_t j = j0 + t; j < j1; j += blockDim.x) {
+    const float2v z = zval(a, j), y = a.y[j];
+    if (mode == 0) {
+      const float2v yx = a.yx[j];
+      const double dx = static_cast<double>(z.x) - y.x, dy = static_cast<double>(z.y) - y.y;
+      const double ex = static_cast<double>(y.x) - yx.x, ey = static_cast<double>(y.y) - yx.y;
+      s0 += dx * dx + dy * dy;
+      s1 += ex * ex + ey * ey;
+      s2 = fmax(s2, static_cast<double>(a.U[j]));
+      continue;
+    }
+    const float2v prev = first ? z : a.p[j];
+    const float2v p{static_cast<float>(y.x + f * (static_cast<double>(prev.x) - y.x)),
+                    static_cast<float>(y.y + f * (static_cast<double>(prev.y) - y.y))};
     const float u = a.U[j];
-    return float2v{v.x / u + c.x, v.y / u + c.y};
-  };
-  double umax = 0.0, d2 = 0.0, r2 = 0.0;
-  for (int64_t j = j0 + t; j < j1; j += nt) {
-    const float2v z = zval(j), y = a.y[j], yx = a.yx[j];
-    umax = fmax(umax, static_cast<double>(a.U[j]));
-    const double dx = static_cast<double>(z.x) - y.x, dy = static_cast<double>(z.y) - y.y;
-    d2 += dx * dx + dy * dy;
-    const double ex = static_cast<double>(y.x) - yx.x, ey = static_cast<double>(y.y) - yx.y;
-    r2 += ex * ex + ey * ey;
-  }
-  umax = block_max(umax, red);
-  d2 = block_sum(d2, red);
-  r2 = block_sum(r2, red);
-  const double eps = a.eps[l];
-  // p = P_B(z)
-  double f = d2 > eps * eps ? eps / sqrt(d2) : 1.0;
-  for (int64_t j = j0 + t; j < j1; j += nt) {
-    const float2v z = zval(j), y = a.y[j];
-    a.p[j] = float2v{static_cast<float>(y.x + f * (static_cast<double>(z.x) - y.x)),
-                     static_cast<float>(y.y + f * (static_cast<double>(z.y) - y.y))};
-  }
-  const float gamma = umax > 0.0 ? static_cast<float>(1.0 / umax) : 0.0f;
-  for (int s = 0; s < a.n_sub; ++s) {
-    // q = p - gamma U (p - z), stored in p; then p = P_B(q)
-    double q2 = 0.0;
-    for (int64_t j = j0 + t; j < j1; j += nt) {
-      const float2v z = zval(j), y = a.y[j], p = a.p[j];
-      const float g = gamma * a.U[j];
+    if (mode == 1) {
+      const float g = static_cast<float>(gamma) * u;
       const float2v q{p.x - g * (p.x - z.x), p.y - g * (p.y - z.y)};
       a.p[j] = q;
       const double dx = static_cast<double>(q.x) - y.x, dy = static_cast<double>(q.y) - y.y;
-      q2 += dx * dx + dy * dy;
+      s0 += dx * dx + dy * dy;
+    } else {
+      a.v[j] = float2v{u * (z.x - p.x), u * (z.y - p.y)};
     }
-    q2 = block_sum(q2, red);
-    f = q2 > eps * eps ? eps / sqrt(q2) : 1.0;
-    for (int64_t j = j0 + t; j < j1; j += nt) {
-      const float2v q = a.p[j], y = a.y[j];
-      a.p[j] = float2v{static_cast<float>(y.x + f * (static_cast<double>(q.x) - y.x)),
-                       static_cast<float>(y.y + f * (static_cast<double>(q.y) - y.y))};
-    }
-    __syncthreads();
   }
-  // v <- U (z - p)
-  for (int64_t j = j0 + t; j < j1; j += nt) {
-    const float2v z = zval(j), p = a.p[j];
-    const float u = a.U[j];
-    a.v[j] = float2v{u * (z.x - p.x), u * (z.y - p.y)};
+  if (mode == 2) return;  // (uniform: no partial sums)
+  s0 = block_sum(s0, red);
+  if (mode == 0) {
+    s1 = block_sum(s1, red);
+    s2 = block_max(s2, red);
   }
-  if (t == 0 && a.residual) a.residual[l] = sqrt(r2);
+  if (t == 0) {
+    double *pp = a.part + (static_cast<int64_t>(l) * kDualBlocks + blk) * 4;
+    pp[0] = s0;
+    pp[1] = s1;
+    pp[2] = s2;
+  }
+}
+
+// one thread per channel: the workgroups' partial sums in order
+__global__ void __launch_bounds__(64) dual_finalize_kernel(DualArgs a, int mode) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= a.L) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int b = 0; b < kDualBlocks; ++b) {
+    const double *pp = a.part + (static_cast<int64_t>(l) * kDualBlocks + b) * 4;
+    s0 += pp[0];
+    s1 += pp[1];
+    s2 = fmax(s2, pp[2]);
+  }
+  const double eps = a.eps[l];
+  a.chs[4 * l] = s0 > eps * eps ? eps / sqrt(s0) : 1.0;
+  if (mode == 0) {
+    a.chs[4 * l + 1] = s2 > 0.0 ? 1.0 / s2 : 0.0;
+    a.chs[4 * l + 2] = sqrt(s1);
+    if (a.residual) a.residual[l] = sqrt(s1);
+  }
 }
 
 int check(const char *what) {
@@ -312,14 +349,23 @@ int launch_degrid(const InterpArgs &a, void *stream) {
 }
 
 int launch_grid(const InterpArgs &a, void *stream) {
-  if (a.m <= 0) return FHS_OK;
-  hipLaunchKernelGGL(grid_kernel, dim3(static_cast<unsigned>((a.m + 255) / 256)), dim3(256), 0,
+  if (a.n_items <= 0) return FHS_OK;
+  if (a.n_items > 0x7fffffff) return fail(FHS_EUNSUPPORTED, "too many gridding work items");
+  hipLaunchKernelGGL(grid_kernel, dim3(static_cast<unsigned>(a.n_items)), dim3(256), 0,
                      static_cast<hipStream_t>(stream), a);
   return check("nufft grid");
 }
 
-int launch_data_dual(const DualArgs &a, int L, void *stream) {
-  hipLaunchKernelGGL(data_dual_kernel, dim3(L), dim3(kDualThreads), 0, static_cast<hipStream_t>(stream), a);
+int launch_data_dual(const DualArgs &a, void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const dim3 grid(kDualBlocks, a.L), fin((a.L + 63) / 64);
+  hipLaunchKernelGGL(dual_pass_kernel, grid, dim3(kDualThreads), 0, s, a, 0, 1);
+  hipLaunchKernelGGL(dual_finalize_kernel, fin, dim3(64), 0, s, a, 0);
+  for (int it = 0; it < a.n_sub; ++it) {
+    hipLaunchKernelGGL(dual_pass_kernel, grid, dim3(kDualThreads), 0, s, a, 1, it == 0 ? 1 : 0);
+    hipLaunchKernelGGL(dual_finalize_kernel, fin, dim3(64), 0, s, a, 1);
+  }
+  hipLaunchKernelGGL(dual_pass_kernel, grid, dim3(kDualThreads), 0, s, a, 2, a.n_sub == 0 ? 1 : 0);
   return check("data dual update");
 }
 
