@@ -220,6 +220,11 @@ def main():
                          "projection) on a 1024x2048x20 cube instead of the facet step")
     ap.add_argument("--vis-per-channel", type=int, default=1 << 20)
     ap.add_argument("--n-sub", type=int, default=10, help="forward-backward sub-iterations of the projection")
+    ap.add_argument("--pdfb-graph", type=int, default=0, metavar="N",
+                    help="time N whole PDFB iterations (identity data term) captured in one HIP graph on the "
+                         "workload (default workload then: 2048x2048x100, 10 sub-cubes)")
+    ap.add_argument("--spectral-overlap", type=int, default=0, metavar="O",
+                    help="with --pdfb-graph: contiguous sub-cubes whose low-rankness facets overlap by O channels")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of the "
@@ -228,6 +233,8 @@ def main():
 
     if args.data_block:
         return data_block_bench(args)
+    if args.pdfb_graph:
+        return pdfb_graph_bench(args)
 
     import synth
     w = synth.WORKLOADS[args.workload]
@@ -449,6 +456,79 @@ def data_block_bench(args):
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "bytes_per_call": algo}}
     log(f"[bench] data block: {ms:.3f} ms per call, {dp.m / (ms / 1e3) / 1e9:.2f} G visibilities/s")
+    print(json.dumps(line), flush=True)
+
+
+def pdfb_graph_bench(args):
+    """N whole PDFB iterations (facet step, identity data term, primal update,
+    extrapolation; Alg. 2 with the denoising stand-in) captured in one HIP graph,
+    replayed from the same start; value = voxels per second per iteration.
+    With --spectral-overlap the sub-cubes are contiguous channel blocks whose
+    low-rankness facets overlap by that many channels."""
+    import torch
+
+    import paper_2003_07358_amd as fhs
+    import synth
+    name = args.workload if args.workload != DEFAULT_WORKLOAD else "cfg4_2048x2048x100_c10"
+    w = synth.WORKLOADS[name]
+    o = args.spectral_overlap
+    n = args.pdfb_graph
+    X = synth.workload_cube(w)
+    plan = fhs.Plan(w.ny, w.nx, w.L, w.qy, w.qx, w.C, w.overlap, w.overlap, w.levels,
+                    spectral_overlap=o).attach_workspace()
+    s = plan.sizes
+    mu, mub = plan.heuristics(synth.sigma_bar(X))
+    seed = synth.BASE_SEED + w.seed_offset
+    theta = synth.uniform_weights(s["n_theta"], seed + 11)
+    tbar = np.concatenate([synth.sorted_weights(plan.Ln, seed + 100 + f) for f in range(s["n_facets"])])
+    y, sig = synth.noisy_data(X, 0.05, seed + 4077)
+    npix = w.ny * w.nx
+    eps = np.full(w.L, sig * np.sqrt(npix + 2.0 * np.sqrt(npix)))   # eps^2 = sigma^2 (N + 2 sqrt(N)), Sec. 2.2
+    x0 = np.maximum(y, 0.0).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    const = dict(y=dev(y), eps=dev(eps), theta=dev(theta), theta_bar=dev(tbar), mu=dev(mu), mu_bar=dev(mub))
+    del X, y
+    t = dict(x=dev(x0), xcheck=dev(x0), p=torch.zeros(s["n_p"], dtype=torch.float32, device="cuda"),
+             w=torch.zeros(s["n_w"], dtype=torch.float32, device="cuda"),
+             v=torch.zeros(s["n_x"], dtype=torch.float32, device="cuda"),
+             grad=torch.empty(s["n_x"], dtype=torch.float32, device="cuda"),
+             xi=torch.zeros(n * w.C, dtype=torch.float64, device="cuda"))
+    init = {k: v.clone() for k, v in t.items()}
+    state = plan.pdfb_state(**t, **const)
+    log(f"[bench] {name}: {n} PDFB iterations in one graph (spectral overlap {o})")
+    graph = plan.pdfb_graph(state, n)
+    times = []
+    for rep in range(1 + max(1, args.steps // 10)):
+        for k in t:
+            t[k].copy_(init[k])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        if rep:
+            times.append(e0.elapsed_time(e1) / n)
+    graph.close()
+    ms = float(np.median(times))
+    xi = t["xi"].view(n, w.C).cpu().numpy()
+    vox = w.ny * w.nx * w.L
+    sb = step_bytes(plan) + 44 * vox           # the facet step plus the closure passes (32 + 12 B/voxel)
+    achieved = sb / (ms / 1e3) / 1e9
+    line = {"metric": "PDFB iterations (identity data term) in one HIP graph: voxels/s per iteration",
+            "value": vox / (ms / 1e3), "unit": "voxels/s", "n_gpus": 1, "steps": n, "warmup": 1,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 (filters, Gram and reconstruction accumulated in f64)",
+            "data": "synthetic (seeded Gaussian-blob cube with power-law spectra, 5 % noise)",
+            "config": {"workload": name, "ny": w.ny, "nx": w.nx, "channels": w.L, "facets": [w.qy, w.qx],
+                       "subcubes": w.C, "spectral": "contiguous blocks, overlap %d channels" % o if o else
+                       "interleaved sub-cubes", "graph_iterations": n, "weights": "random",
+                       "parallelism": "single GPU"},
+            "roofline": {"kernel": "whole iteration", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "bytes_per_iteration": sb},
+            "xi_first_last": [float(xi[0].max()), float(xi[-1].max())]}
+    log(f"[bench] {ms:.3f} ms per iteration in the graph; xi {xi[0].max():.3e} -> {xi[-1].max():.3e}")
     print(json.dumps(line), flush=True)
 
 
