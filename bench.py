@@ -212,6 +212,8 @@ def main():
                          "per-facet execution form, one launch per facet and operator")
     ap.add_argument("--tuning", default=None, metavar="JSON",
                     help="fixed launch shapes (a JSON object as printed in the 'tuning' field) instead of autotuning")
+    ap.add_argument("--tuning-cache", default=None, metavar="PATH",
+                    help="JSON cache of autotuned launch shapes (a hit skips the tuning)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (the reference "
                          "dispatch that scales HBM counters read under rocprofv3 --pmc)")
@@ -310,7 +312,7 @@ def main():
         # launch shapes picked on the workload itself (outside the timed region);
         # the duals it scribbles on are reset afterwards
         t0a = time.perf_counter()
-        tuning = plan.autotune(x_d, p_d, w_d, th_d, tb_d, mu_d, mub_d, g_d, reps=5)
+        tuning = plan.autotune(x_d, p_d, w_d, th_d, tb_d, mu_d, mub_d, g_d, reps=5, cache=args.tuning_cache)
         p_d.zero_()
         w_d.zero_()
         torch.cuda.synchronize()

@@ -6,6 +6,7 @@ C ABI; every step of the computation runs in the library's HIP kernels.  There
 is no fallback: if libfhs.so is missing, using the binding raises FhsError.
 """
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -259,11 +260,29 @@ class Plan:
                 setattr(t, n, int(v))
         _check(self._lib.fhs_plan_set_tuning(self._p, ctypes.byref(t)))
 
-    def autotune(self, xcheck, p, w, theta, theta_bar, mu, mu_bar, grad, reps=3):
+    def tuning_key(self, device=None):
+        """Key of this plan's tuned launch shapes in a cache: device name,
+        library version and the plan configuration."""
+        import torch
+        name = torch.cuda.get_device_name(device)
+        c = self.cfg
+        return (f"{name}|fhs{self._lib.fhs_version()}|{c.ny}x{c.nx}x{c.nchan}|q{c.qy}x{c.qx}|C{c.n_sub}|"
+                f"o{c.overlap_y},{c.overlap_x}|lev{c.levels}|prec{c.precision}|so{c.spectral_overlap}")
+
+    def autotune(self, xcheck, p, w, theta, theta_bar, mu, mu_bar, grad, reps=3, cache=None):
         """Times candidate launch shapes on these arrays and keeps the fastest
-        (p, w and grad are overwritten: pass scratch copies)."""
+        (p, w and grad are overwritten: pass scratch copies).  cache: path of a
+        JSON file of tuned shapes by tuning_key(); a hit sets the stored shapes
+        without timing anything, a miss tunes and adds the result."""
         import torch
         self._need_ws()
+        key = self.tuning_key(xcheck.device) if cache else None
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                entries = json.load(fh)
+            if key in entries:
+                self.tuning = entries[key]
+                return self.tuning
         s = self.sizes
         _check(self._lib.fhs_plan_autotune(
             self._p, self._t(xcheck, s["n_x"], torch.float32, "xcheck"),
@@ -272,6 +291,16 @@ class Plan:
             self._t(theta_bar, s["n_theta_bar"], torch.float64, "theta_bar"),
             self._t(mu, self.C, torch.float64, "mu"), self._t(mu_bar, s["n_facets"], torch.float64, "mu_bar"),
             self._t(grad, s["n_x"], torch.float32, "grad"), int(reps), _stream(xcheck)))
+        if cache:
+            entries = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    entries = json.load(fh)
+            entries[key] = self.tuning
+            tmp = f"{cache}.{os.getpid()}.tmp"
+            with open(tmp, "w") as fh:
+                json.dump(entries, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
         return self.tuning
 
     # ------------------------------------------------------------ device side

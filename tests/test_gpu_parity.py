@@ -306,6 +306,28 @@ def test_autotune_keeps_results():
     check("G", got[2], G.reshape(-1))
 
 
+def test_autotune_cache(tmp_path):
+    """A cache miss tunes and stores the shapes under the plan's key; a hit on
+    a fresh plan of the same configuration sets them without timing."""
+    import json
+    pb, plan = make("ragged_101x77x6_q3x2_c2")
+    cache = str(tmp_path / "tuning.json")
+    args = [dev(pb.theta_flat()), dev(pb.theta_bar_flat()), dev(pb.mu), dev(pb.mu_bar_flat())]
+    x = dev(pb.X)
+    scratch = [dev(pb.P_flat()), dev(pb.W_flat()), torch.empty(plan.sizes["n_x"], device="cuda")]
+    t1 = plan.autotune(x, scratch[0], scratch[1], *args, scratch[2], reps=1, cache=cache)
+    entries = json.load(open(cache))
+    assert entries == {plan.tuning_key(): t1}
+    fresh = fhs.Plan(*pb.cfg).attach_workspace()
+    fresh.tuning = {"nuc_seg": 16, "ana_phase": 1}          # differs from what is stored
+    poison = [torch.full_like(a, float("nan")) for a in scratch]
+    t2 = fresh.autotune(x, poison[0], poison[1], *args, poison[2], reps=1, cache=cache)
+    assert t2 == t1
+    assert all(torch.isnan(a).all() for a in poison)     # a hit runs nothing on the scratch arrays
+    other = fhs.Plan(*pb.cfg, precision=1).attach_workspace()
+    assert other.tuning_key() != plan.tuning_key()
+
+
 @pytest.mark.parametrize("name", ["cfg1_256x256x20_q2x2_o32", "ragged_101x77x6_q3x2_c2", "c4_64x64x12_q4x4_o0"])
 def test_per_facet_form_matches_batched(name):
     """The per-facet execution form computes the same step as the batched one
