@@ -79,10 +79,14 @@ __device__ __forceinline__ void drain_loads() { asm volatile("s_waitcnt vmcnt(0)
 
 // Sum over the segment of `lcp` lanes holding this lane, every lane of the
 // segment receiving the sum (dense widths: see seg_sum).  Power-of-two widths
-// (aligned segments): a butterfly with cross-lane moves that stay in the VALU
-// where possible: DPP quad permutations (lane ^ 1, lane ^ 2), DPP half-row and
-// row mirrors (which pair the two halves of 8 and of 16 lanes), a ds_swizzle
-// xor 16 and, for 64 lanes, a bpermute.
+// (aligned segments): a butterfly whose cross-lane moves all stay in the VALU:
+// DPP quad permutations (lane ^ 1, lane ^ 2), DPP half-row and row mirrors
+// (which pair the two halves of 8 and of 16 lanes), then the gfx950 row swaps:
+// v_permlane16_swap of a value with itself leaves rows (0, 0, 2, 2) in one
+// result and (1, 1, 3, 3) in the other, so their sum is the 32-lane pair sum
+// in every lane; v_permlane32_swap does the same for the two halves of the
+// wave.  (Addition is commutative bit for bit, so every lane of a segment
+// gets the same sum.)
 // (update_dpp with bound_ctrl lets the compiler fold the move into the add:
 // one v_add_f32 with a DPP source)
 __device__ __forceinline__ float dpp_add(float v, int ctrl_tag) {
@@ -139,8 +143,16 @@ __device__ __forceinline__ float seg_sum(float v, int lcp) {
   if (lcp >= 4) v = dpp_add(v, 1);
   if (lcp >= 8) v = dpp_add(v, 2);
   if (lcp >= 16) v = dpp_add(v, 3);
-  if (lcp >= 32) v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));  // lane ^ 16
-  if (lcp >= 64) v += __shfl_xor(v, 32, 64);
+  if (lcp >= 32) {
+    const unsigned u = __float_as_uint(v);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  if (lcp >= 64) {
+    const unsigned u = __float_as_uint(v);
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
   return v;
 }
 

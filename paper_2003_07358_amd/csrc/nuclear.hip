@@ -140,6 +140,67 @@ __device__ __forceinline__ double zval(const NucArgs &A, const float *buf, const
 
 constexpr int kMaxSeg = 64;  // pixels per segment (upper bound)
 
+// One sub-cube with L a multiple of 4 (the common case): the X and P runs of a
+// segment (n pixels x L floats, contiguous in HBM) are copied in 16-byte chunks
+// into rows of Lp floats, X first, then P at word `preg`; chunk i covers the
+// 4-float groups u = 64 i + lane, row u / (Lp / 4).  A row stride that is a
+// multiple of 16 words would put the pixels an MFMA operand reads (same
+// channel, rows 1 or 4 apart) in one LDS bank, so such strides get four words
+// of padding.  The per-lane source offsets do not depend on the segment (rows
+// past its end fall outside the run and read zero), so each wave computes
+// those of its chunks i = wave + 4 t once.
+__host__ __device__ __forceinline__ int one_stride(int L) { return L % 16 == 0 ? L + 4 : L; }
+// floats of one staged array (X or P) of S pixels: whole 256-float copy chunks
+__host__ __device__ __forceinline__ int one_region(int S, int L) { return (S * one_stride(L) + 255) / 256 * 256; }
+
+// The Gram kernel stages through OneStage for one sub-cube without spectral
+// overlap and L a multiple of 4.
+__host__ __device__ __forceinline__ bool gram_one_stage(const NucGeom &g) {
+  return g.C == 1 && !g.spec && g.L % 4 == 0;
+}
+
+struct OneStage {
+  static constexpr int kMaxChunks = 5;  // 16-byte copy chunks per wave and array (ceil(17 / 4))
+  int coff[kMaxChunks];
+  int nchunk, preg, Lp;
+  __device__ __forceinline__ void init(int S, int L, int wave, int ln) {
+    Lp = one_stride(L);
+    preg = one_region(S, L);
+    const int gp = Lp / 4;
+    nchunk = (S * gp + 63) / 64;
+#pragma unroll
+    for (int t = 0; t < kMaxChunks; ++t) {
+      const int u = 64 * (wave + 4 * t) + ln, r = u / gp, gg = u - r * gp;
+      coff[t] = (gg < L / 4 && r < S) ? (r * L + 4 * gg) * 4 : static_cast<int>(0x80000000u);
+    }
+  }
+  // copies of segment sg (P too when with_p) and its window weights
+  __device__ __forceinline__ void issue(const NucArgs &A, const FacetView &F, const Seg &sg, float *buf, double *dd,
+                                        bool with_p, int wave) const {
+    const NucGeom &g = A.g;
+    const int L = g.L;
+    const float *xs = A.x + (static_cast<int64_t>(F.wy0 + sg.y) * g.nx + F.wx0 + sg.s0) * L;
+    const fhs_int32x4 rx = buffer_rsrc(xs, static_cast<unsigned>(sg.n * L * 4));
+    fhs_int32x4 rp = rx;
+    if (with_p) {
+      const float *ps = A.p + F.poff + (static_cast<int64_t>(sg.y) * F.hx + sg.s0) * L;
+      rp = buffer_rsrc(ps, static_cast<unsigned>(sg.n * L * 4));
+    }
+#pragma unroll
+    for (int t = 0; t < kMaxChunks; ++t) {
+      const int i = wave + 4 * t;
+      if (i < nchunk) {
+        fhs_raw_buffer_load_lds(rx, lds_words(buf + 256 * i), 16, coff[t], 0, 0, 0);
+        if (with_p) fhs_raw_buffer_load_lds(rp, lds_words(buf + preg + 256 * i), 16, coff[t], 0, 0, 0);
+      }
+    }
+    if (threadIdx.x < A.seg) {
+      const int i = threadIdx.x;
+      dd[i] = i < sg.n ? ramp(sg.y, F.sy, g.qy, g.oy, F.hy) * ramp(sg.s0 + i, F.sx, g.qx, g.ox, F.hx) : 0.0;
+    }
+  }
+};
+
 // block pairs (bi <= bj) of NB 16-channel blocks
 template <int NB>
 struct Pairs {
@@ -177,10 +238,26 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
   const int y1 = min(y0 + A.chunk_wrows, F.hy);
   const int S = A.seg, L = g.L;
   const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;
-  const int BUF = stage_words(g, S);
   const bool with_p = A.p != nullptr;
-  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
   const int c0 = blockIdx.z * K, nc = min(K, g.C - c0);
+  // one sub-cube, L a multiple of 4: padded rows (OneStage), X row r at r Lp,
+  // P row r at preg + r Lp; else X [S][L] then P [C][S][L_c]
+  const bool one = gram_one_stage(g);
+  OneStage st;
+  st.init(S, L, wave, ln);
+  const int BUF = one ? 2 * st.preg : stage_words(g, S);
+  const int xrs = one ? st.Lp : L;  // X row stride
+  auto issue = [&](const Seg &sg, float *buf, double *dd) __attribute__((always_inline)) {
+    if (one)
+      st.issue(A, F, sg, buf, dd, with_p, wave);
+    else
+      issue_seg(A, F, sg, buf, dd, with_p);
+  };
+  // word of P row r, channel ch of sub-cube c in a staging buffer
+  auto pword = [&](int c, int r, int ch) __attribute__((always_inline)) {
+    return one ? st.preg + r * st.Lp + ch : S * L + (c * S + r) * g.Lc + ch;
+  };
   if (A.sel != nullptr) {  // randomized step: no selected facet among these sub-cubes
     bool any = false;
     for (int kc = 0; kc < nc; ++kc) any = any || A.sel[(c0 + kc) * Q + q] != 0;
@@ -193,10 +270,10 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
 #pragma unroll
     for (int t = 0; t < PR::n; ++t) acc[kc][t] = Acc{0, 0, 0, 0};
 
-  issue_seg(A, F, seg_of(0, y0, nsx, S, F.hx), sm, dsh[0], with_p);
+  issue(seg_of(0, y0, nsx, S, F.hx), sm, dsh[0]);
   for (int i = 0; i < nseg; ++i) {
     wait_loads_and_sync();
-    if (i + 1 < nseg) issue_seg(A, F, seg_of(i + 1, y0, nsx, S, F.hx), sm + ((i + 1) & 1) * BUF, dsh[(i + 1) & 1], with_p);
+    if (i + 1 < nseg) issue(seg_of(i + 1, y0, nsx, S, F.hx), sm + ((i + 1) & 1) * BUF, dsh[(i + 1) & 1]);
     const float *buf = sm + (i & 1) * BUF;
     const double *d = dsh[i & 1];
     const int n = seg_of(i, y0, nsx, S, F.hx).n;
@@ -208,6 +285,18 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
           if (kc < nc) {
             const int c = c0 + kc, ch0 = ln & 15;
             v4s z[NB];
+            // unconditional reads (channel clamped into the sub-cube, rows
+            // below S), then a select, as in the FP64 form
+            float xv[NB][4], pv[NB][4];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              const int ch = min(16 * b + ch0, g.Lc - 1);
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                xv[b][t] = buf[(rb + t) * xrs + c + ch * g.C];
+                pv[b][t] = with_p ? buf[pword(c, rb + t, ch)] : 0.0f;
+              }
+            }
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
               const bool chv = 16 * b + ch0 < g.Lc;
@@ -215,9 +304,8 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
               for (int t = 0; t < 4; ++t) {
                 const int r = rb + t;
                 const bool ok = chv && r < n;
-                const float xv = ok ? buf[r * L + c + (16 * b + ch0) * g.C] : 0.0f;
-                const float pv = (ok && with_p) ? buf[S * L + (c * S + r) * g.Lc + 16 * b + ch0] : 0.0f;
-                z[b][t] = bf16_bits(ok ? fmaf(static_cast<float>(d[r]), xv, pv) : 0.0f);
+                const float zz = fmaf(static_cast<float>(d[r]), xv[b][t], pv[b][t]);
+                z[b][t] = bf16_bits(ok ? zz : 0.0f);
               }
             }
             int t = 0;
@@ -231,7 +319,10 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
       }
     } else {
       for (int k4 = wave; k4 < S / 4; k4 += 4) {
-        const int r = 4 * k4 + ln / 16;
+        // (any split of the rows into groups of four gives the same Gram; with
+        // padded rows the four rows k4 % 4 + 16 (k4 / 4) + 4 j, j = lane / 16,
+        // put the 64 words an operand read takes in distinct LDS banks)
+        const int r = one ? 16 * (k4 >> 2) + (k4 & 3) + 4 * (ln / 16) : 4 * k4 + ln / 16;
         const bool rv = r < n;
         const double dr = d[r];
 #pragma unroll
@@ -239,18 +330,26 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
           if (kc < nc) {
             // Z[r][ch] = P_c[r][ch] + D_r X[r][c + ch C], ch = 16 b + (ln % 16)
             const int c = c0 + kc, ch0 = ln & 15;
-            const float *pr = buf + S * L + (c * S + r) * g.Lc + ch0;
             double z[NB];
             if constexpr (SPEC) {
 #pragma unroll
               for (int b = 0; b < NB; ++b) z[b] = rv ? zval<true>(A, buf, d, n, with_p, c, r, 16 * b + ch0) : 0.0;
             } else {
-              const float *xr = buf + r * L + c + ch0 * g.C;
+              // unconditional reads (channel clamped into the sub-cube, rows
+              // below S), so that they issue back to back; the select zeroes
+              // rows past the segment and channels past L_c
+              float xv[NB], pv[NB];
+#pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                const int ch = min(16 * b + ch0, g.Lc - 1);
+                xv[b] = buf[r * xrs + c + ch * g.C];
+                pv[b] = with_p ? buf[pword(c, r, ch)] : 0.0f;
+              }
 #pragma unroll
               for (int b = 0; b < NB; ++b) {
                 const bool ok = rv && 16 * b + ch0 < g.Lc;
-                const double pv = with_p ? static_cast<double>(pr[16 * b]) : 0.0;
-                z[b] = ok ? fma(dr, static_cast<double>(xr[16 * b * g.C]), pv) : 0.0;
+                const double zz = fma(dr, static_cast<double>(xv[b]), static_cast<double>(pv[b]));
+                z[b] = ok ? zz : 0.0;
               }
             }
             int t = 0;
@@ -467,7 +566,7 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
     const int c = idx / (W * W), r = idx - c * W * W, i = r / W, j = r - (r / W) * W;
     Ks[(c * W + i) * (W + 1) + j] = A.kmat[static_cast<int64_t>(c * Q + q) * A.lc16 * A.lc16 + i * A.lc16 + j];
   }
-  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
   const int nrb = S / 16, ntask = C * nrb;
 
   issue_seg(A, F, seg_of(0, y0, nsx, S, F.hx), stage, dsh[0], true);
@@ -528,23 +627,12 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
 // be long.  Wave w computes channel block w % NB of the row blocks
 // w / NB, w / NB + RW, ... (RW = 4 / NB waves share a block; for NB = 3 the
 // fourth wave idles).
-// Row stride (floats) of the staged X and P segments of nuc_recon1: a row
-// stride that is a multiple of 16 words would put the 16 pixels an MFMA
-// operand reads (same channel) in the same LDS bank, so such strides get four
-// words of padding.
-__host__ __device__ __forceinline__ int recon1_stride(int L) { return L % 16 == 0 ? L + 4 : L; }
-// floats of one staged array (X or P) of S pixels on the 16-byte path: whole
-// 256-float copy chunks
-__host__ __device__ __forceinline__ int recon1_region(int S, int L) {
-  return (S * recon1_stride(L) + 255) / 256 * 256;
-}
 
 template <int NB>
 __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   constexpr int W = NB * 16;
   constexpr int RW = NB >= 4 ? 1 : 4 / NB;
   constexpr int MAXRB = kMaxSeg / 16;  // row blocks per segment, upper bound
-  constexpr int kMaxChunks = 5;        // 16-byte copy chunks per wave and array (ceil(17 / 4))
   extern __shared__ float sm[];
   __shared__ double dsh[2][kMaxSeg];
   const NucGeom &g = A.g;
@@ -556,9 +644,8 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   if (A.active != nullptr && A.active[0] == 0) return;  // the one sub-cube is frozen: P stays
   if (A.sel != nullptr && A.sel[q] == 0) return;        // an unselected facet keeps its P
   const int S = A.seg, L = g.L, Lc = g.Lc;
-  const int Lp = recon1_stride(L);
   const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;
-  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
   const bool active = wave < NB * RW;
   const int mb = wave % NB, rres = wave / NB;
   const int nrb = S / 16;
@@ -567,47 +654,20 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   for (int kk = 0; kk < W / 4; ++kk)
     kr[kk] = A.kmat[static_cast<int64_t>(q) * A.lc16 * A.lc16 + (4 * kk + ln / 16) * A.lc16 + 16 * mb + (ln & 15)];
 
-  // Staging: with L a multiple of 4 the X and P runs of a segment (n pixels
-  // x L floats, contiguous in HBM) are copied in 16-byte chunks into rows of
-  // Lp floats; chunk i covers the 4-float groups u = 64 i + lane, row u / (Lp / 4).
-  // The per-lane source offsets do not depend on the segment (rows past its
-  // end fall outside the run and read zero), so each wave computes those of
-  // its chunks i = wave + 4 t once.
+  // staging: the padded 16-byte path (OneStage) when L is a multiple of 4,
+  // else rows of L floats (X, then P at S L)
   const bool vec = L % 4 == 0;
-  const int gp = Lp / 4, nchunk = (S * gp + 63) / 64;
-  // X then P, each in whole chunks (the 16-byte path) or S rows of L floats
-  const int preg = vec ? recon1_region(S, L) : S * L;
+  OneStage st;
+  st.init(S, L, wave, ln);
+  const int preg = vec ? st.preg : S * L;
   const int BUF = 2 * preg;
-  int coff[kMaxChunks];
-#pragma unroll
-  for (int t = 0; t < kMaxChunks; ++t) {
-    const int u = 64 * (wave + 4 * t) + ln, r = u / gp, gg = u - r * gp;
-    coff[t] = (gg < L / 4 && r < S) ? (r * L + 4 * gg) * 4 : static_cast<int>(0x80000000u);
-  }
+  const int rs = vec ? st.Lp : L;
   auto issue = [&](const Seg &sg, float *buf, double *dd) __attribute__((always_inline)) {
-    if (!vec) {
+    if (vec)
+      st.issue(A, F, sg, buf, dd, true, wave);
+    else
       issue_seg(A, F, sg, buf, dd, true);
-      return;
-    }
-    const float *xs = A.x + (static_cast<int64_t>(F.wy0 + sg.y) * g.nx + F.wx0 + sg.s0) * L;
-    const float *ps = A.p + F.poff + (static_cast<int64_t>(sg.y) * F.hx + sg.s0) * Lc;
-    const fhs_int32x4 rx = buffer_rsrc(xs, static_cast<unsigned>(sg.n * L * 4));
-    const fhs_int32x4 rp = buffer_rsrc(ps, static_cast<unsigned>(sg.n * L * 4));
-#pragma unroll
-    for (int t = 0; t < kMaxChunks; ++t) {
-      const int i = wave + 4 * t;
-      if (i < nchunk) {
-        fhs_raw_buffer_load_lds(rx, lds_words(buf + 256 * i), 16, coff[t], 0, 0, 0);
-        fhs_raw_buffer_load_lds(rp, lds_words(buf + preg + 256 * i), 16, coff[t], 0, 0, 0);
-      }
-    }
-    if (threadIdx.x < S) {
-      const int i = threadIdx.x;
-      dd[i] = i < sg.n ? ramp(sg.y, F.sy, g.qy, g.oy, F.hy) * ramp(sg.s0 + i, F.sx, g.qx, g.ox, F.hx) : 0.0;
-    }
   };
-  // (the copy_span path keeps rows of L floats)
-  const int rs = vec ? Lp : L;
 
   issue(seg_of(0, y0, nsx, S, F.hx), sm, dsh[0]);
   for (int i = 0; i < nseg; ++i) {
@@ -630,19 +690,31 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
         const float *xr = buf + r * rs + ln / 16, *pr = xr + preg;
         const double dr = d[r];
         v4d res = v4d{0.0, 0.0, 0.0, 0.0};
+        // (the reads are unconditional, so that they issue back to back: every
+        // address lies inside the staging allocation, which has 64 words of
+        // slack past the last buffer; rows past the segment and channels past
+        // L_c are zeroed by the select)
+        float xv[W / 4], pv[W / 4];
 #pragma unroll
         for (int kk = 0; kk < W / 4; ++kk) {
-          // A[m][k] = K[k][m], B[k][n] = Z[n][k]  ->  D[m][n] = (Z K)[n][m]
-          const bool ok = rv && 4 * kk + ln / 16 < Lc;
-          const double z = ok ? fma(dr, static_cast<double>(xr[4 * kk]), static_cast<double>(pr[4 * kk])) : 0.0;
-          res = __builtin_amdgcn_mfma_f64_16x16x4f64(kr[kk], z, res, 0, 0, 0);
+          xv[kk] = xr[4 * kk];
+          pv[kk] = pr[4 * kk];
         }
-        if (r < sg.n) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int m = 16 * mb + 4 * v + ln / 16;
-            if (m < Lc) dst[r * Lc + m] = static_cast<float>(res[v]);
-          }
+        for (int kk = 0; kk < W / 4; ++kk) {
+          // A[n][k] = Z[n][k], B[k][m] = K[k][m]  ->  D[n][m] = (Z K)[n][m]
+          const bool ok = rv && 4 * kk + ln / 16 < Lc;
+          const double zz = fma(dr, static_cast<double>(xv[kk]), static_cast<double>(pv[kk]));
+          const double z = ok ? zz : 0.0;
+          res = __builtin_amdgcn_mfma_f64_16x16x4f64(z, kr[kk], res, 0, 0, 0);
+        }
+        // lane l holds D[4 v + l / 16][l % 16]: each store writes four rows of
+        // 16 consecutive channels
+        const int m = 16 * mb + (ln & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = 16 * nb + 4 * v + ln / 16;
+          if (rr < sg.n && m < Lc) dst[rr * Lc + m] = static_cast<float>(res[v]);
         }
       }
     }
@@ -759,7 +831,11 @@ size_t nuc_lds_bytes(const NucArgs &a, bool recon) {
   // (+64 words: masked-out lanes read up to 63 words past a buffer)
   const size_t pw = static_cast<size_t>(a.g.C) * a.g.Lc;  // P floats per pixel over the sub-cubes
   const size_t stage = (2 * static_cast<size_t>(a.seg) * (a.g.L + pw) + 64) * sizeof(float);
-  if (!recon) return stage > 8192 ? stage : 8192;  // the unit reduction reuses it (4 x 256 doubles)
+  if (!recon) {
+    const size_t gs =
+        gram_one_stage(a.g) ? (2 * 2 * static_cast<size_t>(one_region(a.seg, a.g.L)) + 64) * sizeof(float) : stage;
+    return gs > 8192 ? gs : 8192;  // the unit reduction reuses it (4 x 256 doubles)
+  }
   return static_cast<size_t>(a.g.C) * W * (W + 1) * sizeof(double) + stage +
          static_cast<size_t>(a.seg) * pw * sizeof(float);
 }
@@ -811,7 +887,7 @@ int launch_nuc_recon(const NucArgs &a, int nspatial, void *stream) {
   const dim3 grid(a.chunks, nspatial);
   if (a.g.C == 1) {
     // (+64 words: masked-out lanes read up to 63 words past a buffer)
-    const int preg = a.g.L % 4 == 0 ? recon1_region(a.seg, a.g.L) : a.seg * a.g.L;
+    const int preg = a.g.L % 4 == 0 ? one_region(a.seg, a.g.L) : a.seg * a.g.L;
     const size_t lds1 = static_cast<size_t>(2 * 2 * preg + 64) * sizeof(float);
     switch (a.lc16 / 16) {
       case 1: hipLaunchKernelGGL(nuc_recon1_kernel<1>, grid, dim3(256), lds1, s, a); break;
