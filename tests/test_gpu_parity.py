@@ -261,6 +261,26 @@ def test_bitwise_deterministic():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("name", ["cfg1_256x256x20_q2x2_o32", "ragged_101x77x6_q3x2_c2"])
+def test_stream_schedules_agree(name):
+    """One stream, or the nuclear chain on the side stream beside the wavelet
+    chain: the same kernels on the same data, so the same bits."""
+    pb, plan = make(name, warm=True)
+    outs = []
+    for conc in (0, 1):
+        plan.tuning = {"concurrent": conc}
+        p, w = dev(pb.P_flat()), dev(pb.W_flat())
+        g = torch.empty(plan.sizes["n_x"], device="cuda")
+        plan.facet_prox_step(dev(pb.X), p, w, dev(pb.theta_flat()), dev(pb.theta_bar_flat()), dev(pb.mu),
+                             dev(pb.mu_bar_flat()), 1.0, 1.0, g)
+        outs.append((host(p), host(w), host(g)))
+    for o in outs[1:]:
+        for nm, a, b in zip(("P+", "W+", "G"), o, outs[0]):
+            assert np.array_equal(a, b), nm
+    Pn, Wn, G = pb.oracle_step()
+    check("G (side stream)", outs[1][2], G.reshape(-1))
+
+
 @pytest.mark.slow
 def test_facet_prox_step_cfg2_full():
     """1024 x 2048 x 20, 4 x 4 facets, 64-px overlap: the full FP64 oracle."""
