@@ -622,16 +622,15 @@ __global__ void __launch_bounds__(256) nuc_recon_kernel(NucArgs A) {
   drain_loads();
 }
 
-// One sub-cube (C = 1): each wave keeps the K columns of its 16-channel output
-// block in registers, so LDS holds only the staging buffers and segments can
-// be long.  Wave w computes channel block w % NB of the row blocks
-// w / NB, w / NB + RW, ... (RW = 4 / NB waves share a block; for NB = 3 the
-// fourth wave idles).
+// One sub-cube (C = 1): each wave holds all of K (W x W) in registers and
+// takes whole 16-row blocks of the segment (wave w: blocks w, w + 4, ...): it
+// forms the block's Z once (16 rows x W channels, FP64) and runs the NB output
+// channel blocks as NB interleaved MFMA accumulation chains, so LDS is read
+// once per Z element and no wave waits on a single dependent chain.
 
 template <int NB>
 __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   constexpr int W = NB * 16;
-  constexpr int RW = NB >= 4 ? 1 : 4 / NB;
   constexpr int MAXRB = kMaxSeg / 16;  // row blocks per segment, upper bound
   extern __shared__ float sm[];
   __shared__ double dsh[2][kMaxSeg];
@@ -646,13 +645,15 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
   const int S = A.seg, L = g.L, Lc = g.Lc;
   const int nsx = (F.hx + S - 1) / S, nseg = (y1 - y0) * nsx;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
-  const bool active = wave < NB * RW;
-  const int mb = wave % NB, rres = wave / NB;
   const int nrb = S / 16;
-  double kr[W / 4];
+  // kr[mb][kk] = K[4 kk + lane / 16][16 mb + lane % 16]: the B operand of
+  // output channel block mb, contraction slice kk
+  double kr[NB][W / 4];
+  const double *Kq = A.kmat + static_cast<int64_t>(q) * A.lc16 * A.lc16;
 #pragma unroll
-  for (int kk = 0; kk < W / 4; ++kk)
-    kr[kk] = A.kmat[static_cast<int64_t>(q) * A.lc16 * A.lc16 + (4 * kk + ln / 16) * A.lc16 + 16 * mb + (ln & 15)];
+  for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+    for (int kk = 0; kk < W / 4; ++kk) kr[mb][kk] = Kq[(4 * kk + ln / 16) * A.lc16 + 16 * mb + (ln & 15)];
 
   // staging: the padded 16-byte path (OneStage) when L is a multiple of 4,
   // else rows of L floats (X, then P at S L)
@@ -679,42 +680,43 @@ __global__ void __launch_bounds__(256) nuc_recon1_kernel(NucArgs A) {
     // results go straight from registers to P (rows of other segments are
     // never touched), so the stores drain while later row blocks compute
     float *dst = A.p + F.poff + (static_cast<int64_t>(sg.y) * F.hx + sg.s0) * Lc;
-#pragma unroll
-    for (int j = 0; j < MAXRB; ++j) {
-      const int nb = rres + j * RW;
-      if (active && nb < nrb) {
+#pragma unroll 1
+    for (int j = 0; j < MAXRB; j += 4) {
+      const int nb = wave + j;
+      if (nb < nrb) {
         const int r = 16 * nb + (ln & 15);
         // Z[r][k] = P[r][k] + D_r X[r][k] (one sub-cube: X and P rows have the
-        // same layout), read at compile-time offsets from per-row bases
+        // same layout), read at compile-time offsets from per-row bases; the
+        // reads are unconditional (every address lies inside the staging
+        // allocation, which has 64 words of slack past the last buffer) and a
+        // select zeroes rows past the segment and channels past L_c
         const bool rv = r < sg.n;
         const float *xr = buf + r * rs + ln / 16, *pr = xr + preg;
         const double dr = d[r];
-        v4d res = v4d{0.0, 0.0, 0.0, 0.0};
-        // (the reads are unconditional, so that they issue back to back: every
-        // address lies inside the staging allocation, which has 64 words of
-        // slack past the last buffer; rows past the segment and channels past
-        // L_c are zeroed by the select)
-        float xv[W / 4], pv[W / 4];
+        double z[W / 4];
 #pragma unroll
         for (int kk = 0; kk < W / 4; ++kk) {
-          xv[kk] = xr[4 * kk];
-          pv[kk] = pr[4 * kk];
+          const double zz = fma(dr, static_cast<double>(xr[4 * kk]), static_cast<double>(pr[4 * kk]));
+          z[kk] = (rv && 4 * kk + ln / 16 < Lc) ? zz : 0.0;
         }
+        v4d res[NB];
 #pragma unroll
-        for (int kk = 0; kk < W / 4; ++kk) {
-          // A[n][k] = Z[n][k], B[k][m] = K[k][m]  ->  D[n][m] = (Z K)[n][m]
-          const bool ok = rv && 4 * kk + ln / 16 < Lc;
-          const double zz = fma(dr, static_cast<double>(xv[kk]), static_cast<double>(pv[kk]));
-          const double z = ok ? zz : 0.0;
-          res = __builtin_amdgcn_mfma_f64_16x16x4f64(z, kr[kk], res, 0, 0, 0);
-        }
+        for (int mb = 0; mb < NB; ++mb) res[mb] = v4d{0.0, 0.0, 0.0, 0.0};
+        // A[n][k] = Z[n][k], B[k][m] = K[k][m]  ->  D[n][m] = (Z K)[n][m]
+#pragma unroll
+        for (int kk = 0; kk < W / 4; ++kk)
+#pragma unroll
+          for (int mb = 0; mb < NB; ++mb) res[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(z[kk], kr[mb][kk], res[mb], 0, 0, 0);
         // lane l holds D[4 v + l / 16][l % 16]: each store writes four rows of
         // 16 consecutive channels
-        const int m = 16 * mb + (ln & 15);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int rr = 16 * nb + 4 * v + ln / 16;
-          if (rr < sg.n && m < Lc) dst[rr * Lc + m] = static_cast<float>(res[v]);
+        for (int mb = 0; mb < NB; ++mb) {
+          const int m = 16 * mb + (ln & 15);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int rr = 16 * nb + 4 * v + ln / 16;
+            if (rr < sg.n && m < Lc) dst[rr * Lc + m] = static_cast<float>(res[mb][v]);
+          }
         }
       }
     }
