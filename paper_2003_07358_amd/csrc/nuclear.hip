@@ -317,12 +317,53 @@ __global__ void __launch_bounds__(256) nuc_gram_kernel(NucArgs A) {
           }
         }
       }
+    } else if (!SPEC && one) {
+      // One sub-cube: the wave's row groups k4 = wave, wave + 4, ... taken two
+      // per iteration, the reads of both issued first, so that the second
+      // group's reads land while the first group's MFMAs run (the
+      // accumulation order is that of the plain loop).  Any split of the rows
+      // into groups of four gives the same Gram; with padded rows the four
+      // rows k4 % 4 + 16 (k4 / 4) + 4 j, j = lane / 16, put the 64 words an
+      // operand read takes in distinct LDS banks.
+      const int ch0 = ln & 15;
+      auto rows_of = [&](int k4) { return 16 * (k4 >> 2) + (k4 & 3) + 4 * (ln / 16); };
+      auto load = [&](int r, float(&xv)[NB], float(&pv)[NB]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          // (unconditional reads, channel clamped into the cube, rows below S)
+          const int ch = min(16 * b + ch0, g.Lc - 1);
+          xv[b] = buf[r * st.Lp + ch];
+          pv[b] = with_p ? buf[st.preg + r * st.Lp + ch] : 0.0f;
+        }
+      };
+      auto accumulate = [&](int r, const float(&xv)[NB], const float(&pv)[NB]) __attribute__((always_inline)) {
+        const bool rv = r < n;
+        const double dr = d[r];
+        double z[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const double zz = fma(dr, static_cast<double>(xv[b]), static_cast<double>(pv[b]));
+          z[b] = (rv && 16 * b + ch0 < g.Lc) ? zz : 0.0;
+        }
+        int t = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+          for (int bj = bi; bj < NB; ++bj, ++t)
+            acc[0][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(z[bi], z[bj], acc[0][t], 0, 0, 0);
+      };
+      for (int k4 = wave; k4 < S / 4; k4 += 8) {
+        const bool two = k4 + 4 < S / 4;
+        const int ra = rows_of(k4), rb = rows_of(k4 + 4);
+        float xa[NB], pa[NB], xb[NB], pb[NB];
+        load(ra, xa, pa);
+        if (two) load(rb, xb, pb);
+        accumulate(ra, xa, pa);
+        if (two) accumulate(rb, xb, pb);
+      }
     } else {
       for (int k4 = wave; k4 < S / 4; k4 += 4) {
-        // (any split of the rows into groups of four gives the same Gram; with
-        // padded rows the four rows k4 % 4 + 16 (k4 / 4) + 4 j, j = lane / 16,
-        // put the 64 words an operand read takes in distinct LDS banks)
-        const int r = one ? 16 * (k4 >> 2) + (k4 & 3) + 4 * (ln / 16) : 4 * k4 + ln / 16;
+        const int r = 4 * k4 + ln / 16;
         const bool rv = r < n;
         const double dr = d[r];
 #pragma unroll
