@@ -61,31 +61,62 @@ __global__ void __launch_bounds__(256) crop_kernel(CropArgs a) {
 
 // ---------------------------------------------------------------- F, by rows
 // One workgroup per row of K points (a power of two): the row is copied into
-// LDS and transformed by log2(K) radix-2 Stockham passes (self-sorting, so no
-// bit reversal); pass m (m = K/2, K/4, ..., 1; stride s = K / (2 m)) maps
-// butterfly b = p s + q to
-//   y[q + s 2p] = x[q + s p] + x[q + s (p + m)]
-//   y[q + s (2p + 1)] = (x[q + s p] - x[q + s (p + m)]) W^(p s)
-// with W = exp(sign 2 pi i / K), read from the table of exp(-2 pi i k / K).
+// LDS and transformed by Stockham passes (self-sorting, so no bit reversal):
+// floor(log4 K) radix-4 passes, then one radix-2 pass when log2 K is odd.
+// A radix-4 pass over blocks of n = 4m points with stride s (s = 1, 4, 16, ...)
+// maps butterfly b = p s + q (p < m, q < s), a_k = x[q + s (p + k m)], to
+//   t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = (a1 - a3) i^(sign)
+//   y[q + s 4p] = t0 + t2,  y[q + s (4p + 2)] = (t0 - t2) W^(2 p s),
+//   y[q + s (4p + 1)] = (t1 + t3) W^(p s),  y[q + s (4p + 3)] = (t1 - t3) W^(3 p s)
+// and the radix-2 pass (m = 1) maps b = p s + q to
+//   y[q + s 2p] = x[q + s p] + x[q + s (p + 1)],  y[q + s (2p + 1)] = (x[q + s p] - x[q + s (p + 1)]) W^(p s),
+// with W = exp(sign 2 pi i / K) from the table of exp(-2 pi i k / K), k < K/2
+// (W^(k + K/2) = -W^k; conjugated for sign > 0).
+__device__ __forceinline__ float2v twiddle(const float2v *tw, int k, int half, int sign) {
+  float2v w = k < half ? tw[k] : float2v{-tw[k - half].x, -tw[k - half].y};
+  if (sign > 0) w.y = -w.y;
+  return w;
+}
+
 __global__ void __launch_bounds__(1024) fft_rows_kernel(float2v *data, int K, const float2v *tw, int sign) {
   extern __shared__ float2v buf[];
   float2v *x = buf, *y = buf + K;
   float2v *row = data + static_cast<int64_t>(blockIdx.x) * K;
   for (int i = threadIdx.x; i < K; i += blockDim.x) x[i] = row[i];
   __syncthreads();
-  for (int m = K / 2, s = 1; m >= 1; m >>= 1, s <<= 1) {
-    for (int b = threadIdx.x; b < K / 2; b += blockDim.x) {
-      const int p = b / s, q = b - p * s;
-      float2v w = tw[p * s];
-      if (sign > 0) w.y = -w.y;
-      const float2v u = x[q + s * p], v = x[q + s * (p + m)];
-      y[q + s * 2 * p] = float2v{u.x + v.x, u.y + v.y};
-      y[q + s * (2 * p + 1)] = cmul(float2v{u.x - v.x, u.y - v.y}, w);
+  const int half = K >> 1;
+  int ls = 0, n = K;  // log2 of the stride, points per block
+  for (; n >= 4; n >>= 2, ls += 2) {
+    const int m = n >> 2, s = 1 << ls;
+    for (int b = threadIdx.x; b < (K >> 2); b += blockDim.x) {
+      const int p = b >> ls, q = b & (s - 1);
+      const float2v a0 = x[q + s * p], a1 = x[q + s * (p + m)], a2 = x[q + s * (p + 2 * m)],
+                    a3 = x[q + s * (p + 3 * m)];
+      const float2v t0{a0.x + a2.x, a0.y + a2.y}, t1{a0.x - a2.x, a0.y - a2.y};
+      const float2v t2{a1.x + a3.x, a1.y + a3.y}, d{a1.x - a3.x, a1.y - a3.y};
+      // d i^(sign): times -i (forward) or +i (inverse)
+      const float2v t3 = sign > 0 ? float2v{-d.y, d.x} : float2v{d.y, -d.x};
+      const int e = p << ls;  // exponent p s
+      y[q + s * 4 * p] = float2v{t0.x + t2.x, t0.y + t2.y};
+      y[q + s * (4 * p + 1)] = cmul(float2v{t1.x + t3.x, t1.y + t3.y}, twiddle(tw, e, half, sign));
+      y[q + s * (4 * p + 2)] = cmul(float2v{t0.x - t2.x, t0.y - t2.y}, twiddle(tw, 2 * e, half, sign));
+      y[q + s * (4 * p + 3)] = cmul(float2v{t1.x - t3.x, t1.y - t3.y}, twiddle(tw, 3 * e, half, sign));
     }
     __syncthreads();
     float2v *t = x;
     x = y;
     y = t;
+  }
+  if (n == 2) {
+    const int s = 1 << ls;
+    for (int b = threadIdx.x; b < half; b += blockDim.x) {
+      const int p = b >> ls, q = b & (s - 1);
+      const float2v u = x[q + s * p], v = x[q + s * (p + 1)];
+      y[q + s * 2 * p] = float2v{u.x + v.x, u.y + v.y};
+      y[q + s * (2 * p + 1)] = cmul(float2v{u.x - v.x, u.y - v.y}, twiddle(tw, p << ls, half, sign));
+    }
+    __syncthreads();
+    x = y;
   }
   for (int i = threadIdx.x; i < K; i += blockDim.x) row[i] = x[i];
 }
@@ -322,7 +353,8 @@ int launch_fft_rows(float2v *data, int64_t rows, int K, const float2v *tw, int s
   if (rows <= 0) return FHS_OK;
   if (K < 2 || K > kMaxGrid || (K & (K - 1)) != 0) return fail(FHS_EUNSUPPORTED, "FFT length must be a power of two");
   if (rows > 0x7fffffff) return fail(FHS_EUNSUPPORTED, "too many FFT rows");
-  const int threads = K / 2 < 1024 ? (K / 2 < 64 ? 64 : K / 2) : 1024;
+  // (one radix-4 butterfly per thread and pass, up to 1024 threads)
+  const int threads = K / 4 < 1024 ? (K / 4 < 64 ? 64 : K / 4) : 1024;
   const size_t lds = static_cast<size_t>(2 * K) * sizeof(float2v);
   hipLaunchKernelGGL(fft_rows_kernel, dim3(static_cast<unsigned>(rows)), dim3(threads), lds,
                      static_cast<hipStream_t>(stream), data, K, tw, sign);
