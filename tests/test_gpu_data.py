@@ -4,9 +4,10 @@ oracle.nufft, through the C ABI.
 
 Bar: relative L2 error <= 1e-5 per output (FP32 FFT and storage, FP64
 interpolation sums and reductions: the FFT's rounding grows as u log2 K, about
-1e-6 here).  Cases: square and rectangular images, several channels whose
-coverages are the reference one scaled by the frequency ratio, a channel
-without visibilities, coverages reaching the grid's wrap-around, the
+1e-6 here).  Cases: square and rectangular images (grid axes with even and odd
+log2, up to the largest, 8192 points), several channels whose coverages are the
+reference one scaled by the frequency ratio, a channel without visibilities,
+coverages reaching the grid's wrap-around, the
 preconditioned update with 0 and several sub-iterations, and an active and
 an inactive l2 ball.
 """
@@ -28,6 +29,7 @@ CASES = {
     "128x128_l2_m3000": dict(ny=128, nx=128, L=2, M=3000, seed=2),
     "32x64_l4_m300_empty": dict(ny=32, nx=64, L=4, M=300, seed=3, empty=2),
     "16x16_l1_wrap": dict(ny=16, nx=16, L=1, M=400, seed=4, wrap=True),
+    "64x4096_l1_m2000_maxgrid": dict(ny=64, nx=4096, L=1, M=2000, seed=5),   # 8192-point FFT rows
 }
 
 
