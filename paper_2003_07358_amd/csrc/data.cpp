@@ -102,6 +102,7 @@ int adjoint(const fhs_data_plan *p, const float2v *vis, float *x, const double *
   ia.m = p->m;
   ia.K1 = p->K1;
   ia.K2 = p->K2;
+  ia.wexp = p->wexp;
   if (int rc = launch_grid(ia, stream)) return rc;
   if (int rc = launch_fft_rows(B, static_cast<int64_t>(p->L) * p->K2, p->K1, wsp<float2v>(p, p->off_tw1), +1, stream))
     return rc;
@@ -196,6 +197,14 @@ int fhs_data_plan_create(const fhs_data_config *cfg, const int64_t *n_vis, const
       ++counts[cell[j]];
     }
   for (int64_t j = 0; j < p->m; ++j) p->density_inv[j] = 1.0 / static_cast<double>(counts[cell[j]]);
+  {
+    // bound on the weight products, for the fixed-point gridding
+    float wm = 0.0f;
+    for (const float x : p->w) wm = std::max(wm, std::fabs(x));
+    int e = 0;
+    std::frexp(static_cast<double>(wm) * static_cast<double>(wm), &e);  // wm^2 < 2^e
+    p->wexp = e;
+  }
   // gridding order: visibilities sorted by (channel, tile of their first grid
   // indices), each run of one tile cut into work items of at most kGridChunk
   {

@@ -62,6 +62,7 @@ struct InterpArgs {
   const GridItem *items;   // gridding work items
   int64_t m, n_items;
   int K1, K2;
+  int wexp;                // gridding: every product of two weights is below 2^wexp
 };
 
 struct DualArgs {
@@ -104,6 +105,7 @@ struct fhs_data_plan {
   std::vector<double> density_inv;     // inverse sampling density per visibility
   std::vector<int32_t> perm;           // visibilities sorted by (channel, grid tile)
   std::vector<fhs::data::GridItem> items;
+  int wexp = 0;                        // every product of two interpolation weights is below 2^wexp
   // workspace layout (bytes)
   int64_t off_a = 0, off_b = 0, off_v1 = 0, off_v2 = 0, off_p = 0, off_info = 0, off_w = 0, off_s1 = 0,
           off_s2 = 0, off_tw1 = 0, off_tw2 = 0, off_voff = 0, off_perm = 0, off_items = 0, off_part = 0,

@@ -129,3 +129,21 @@ def test_data_dual_update(name, n_sub):
     log(f"    n_sub {n_sub}: v+ rel_l2 {ev:.2e}, grad {eg:.2e}, residual {er:.2e}")
     assert np.linalg.norm(vis_concat(Vn)) > 0 and np.max(np.abs(G)) > 0   # some ball is active
     assert ev <= TOL and eg <= TOL and er <= TOL
+
+
+def test_adjoint_carries_a_non_finite_visibility():
+    """A NaN visibility reaches the gridded channel as NaN (the gridding takes
+    its FP32 form for that work item); the other channels stay exact."""
+    X, covs, ops, dp = make("64x32_l3_m500")
+    r = np.random.default_rng(9)
+    v = (r.standard_normal(dp.m) + 1j * r.standard_normal(dp.m)).astype(np.complex64)
+    v[dp.voff[1] + 3] = np.nan
+    xo = torch.zeros(X.shape, dtype=torch.float32, device="cuda")
+    dp.adjoint(dev(v), xo, dev(np.ones(dp.L)), beta=0.0)
+    out = host(xo)
+    assert np.isnan(out[..., 1]).any()
+    for l in (0, 2):
+        ref = ops[l].adjoint(v[dp.voff[l]:dp.voff[l + 1]])
+        e = rel_l2(out[..., l], ref)
+        log(f"    channel {l}: rel_l2 {e:.2e}")
+        assert np.isfinite(out[..., l]).all() and e <= TOL
