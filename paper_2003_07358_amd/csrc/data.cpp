@@ -80,6 +80,7 @@ int forward(const fhs_data_plan *p, const float *x, float2v *vis, void *stream) 
   ia.vis_out = vis;
   ia.info = wsp<VisInfo>(p, p->off_info);
   ia.w = wsp<float>(p, p->off_w);
+  ia.perm = wsp<int32_t>(p, p->off_perm);
   ia.m = p->m;
   ia.K1 = p->K1;
   ia.K2 = p->K2;

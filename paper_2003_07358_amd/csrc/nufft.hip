@@ -147,9 +147,13 @@ __global__ void __launch_bounds__(256) fill_zero_kernel(float2v *d, int64_t n) {
 // ---------------------------------------------------------------- G and G^H
 // One thread per visibility: the J x J grid points from its first indices,
 // wrapped modulo K, weights psi(t1 - k1) psi(t2 - k2) (FP64 accumulation).
+// Threads take the visibilities in the gridding order (sorted by channel and
+// grid tile), so that neighbouring threads read neighbouring grid points
+// through the caches; each result goes to its visibility's own slot.
 __global__ void __launch_bounds__(256) degrid_kernel(InterpArgs a) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= a.m) return;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.m) return;
+  const int64_t j = a.perm[i];
   const VisInfo vi = a.info[j];
   const float *w = a.w + j * 2 * kKbWidth;
   const float2v *plane = a.spec + static_cast<int64_t>(vi.chan) * a.K1 * a.K2;
