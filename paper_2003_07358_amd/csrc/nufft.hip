@@ -11,6 +11,8 @@
 // there; the adjoint path grids into that layout and transposes back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <string>
 
 #include "data_internal.h"
@@ -60,7 +62,7 @@ __global__ void __launch_bounds__(256) crop_kernel(CropArgs a) {
 }
 
 // ---------------------------------------------------------------- F, by rows
-// One workgroup per row of K points (a power of two): the row is copied into
+// Workgroups walk rows of K points (a power of two), each row copied into
 // LDS and transformed by Stockham passes (self-sorting, so no bit reversal):
 // floor(log4 K) radix-4 passes, then one radix-2 pass when log2 K is odd.
 // A radix-4 pass over blocks of n = 4m points with stride s (s = 1, 4, 16, ...)
@@ -78,47 +80,73 @@ __device__ __forceinline__ float2v twiddle(const float2v *tw, int k, int half, i
   return w;
 }
 
-__global__ void __launch_bounds__(1024) fft_rows_kernel(float2v *data, int K, const float2v *tw, int sign) {
+// A workgroup takes rows blockIdx.x, blockIdx.x + gridDim.x, ...: the next
+// row's points are loaded into registers while the passes of the current one
+// run, so the row loads overlap the transform.
+constexpr int kFftMaxPer = kMaxGrid / 1024;  // points per thread and row, upper bound
+
+__global__ void __launch_bounds__(1024) fft_rows_kernel(float2v *data, int64_t rows, int K, const float2v *tw,
+                                                        int sign) {
   extern __shared__ float2v buf[];
-  float2v *x = buf, *y = buf + K;
-  float2v *row = data + static_cast<int64_t>(blockIdx.x) * K;
-  for (int i = threadIdx.x; i < K; i += blockDim.x) x[i] = row[i];
-  __syncthreads();
-  const int half = K >> 1;
-  int ls = 0, n = K;  // log2 of the stride, points per block
-  for (; n >= 4; n >>= 2, ls += 2) {
-    const int m = n >> 2, s = 1 << ls;
-    for (int b = threadIdx.x; b < (K >> 2); b += blockDim.x) {
-      const int p = b >> ls, q = b & (s - 1);
-      const float2v a0 = x[q + s * p], a1 = x[q + s * (p + m)], a2 = x[q + s * (p + 2 * m)],
-                    a3 = x[q + s * (p + 3 * m)];
-      const float2v t0{a0.x + a2.x, a0.y + a2.y}, t1{a0.x - a2.x, a0.y - a2.y};
-      const float2v t2{a1.x + a3.x, a1.y + a3.y}, d{a1.x - a3.x, a1.y - a3.y};
-      // d i^(sign): times -i (forward) or +i (inverse)
-      const float2v t3 = sign > 0 ? float2v{-d.y, d.x} : float2v{d.y, -d.x};
-      const int e = p << ls;  // exponent p s
-      y[q + s * 4 * p] = float2v{t0.x + t2.x, t0.y + t2.y};
-      y[q + s * (4 * p + 1)] = cmul(float2v{t1.x + t3.x, t1.y + t3.y}, twiddle(tw, e, half, sign));
-      y[q + s * (4 * p + 2)] = cmul(float2v{t0.x - t2.x, t0.y - t2.y}, twiddle(tw, 2 * e, half, sign));
-      y[q + s * (4 * p + 3)] = cmul(float2v{t1.x - t3.x, t1.y - t3.y}, twiddle(tw, 3 * e, half, sign));
+  const int nthr = static_cast<int>(blockDim.x);
+  float2v pre[kFftMaxPer];
+  auto fetch = [&](int64_t r) __attribute__((always_inline)) {
+    const float2v *src = data + r * K;
+#pragma unroll
+    for (int t = 0; t < kFftMaxPer; ++t) {
+      const int i = static_cast<int>(threadIdx.x) + t * nthr;
+      if (i < K) pre[t] = src[i];
+    }
+  };
+  int64_t r = blockIdx.x;
+  if (r < rows) fetch(r);
+  for (; r < rows; r += gridDim.x) {
+    float2v *x = buf, *y = buf + K;
+    __syncthreads();  // (the previous row has left the LDS)
+#pragma unroll
+    for (int t = 0; t < kFftMaxPer; ++t) {
+      const int i = static_cast<int>(threadIdx.x) + t * nthr;
+      if (i < K) x[i] = pre[t];
     }
     __syncthreads();
-    float2v *t = x;
-    x = y;
-    y = t;
-  }
-  if (n == 2) {
-    const int s = 1 << ls;
-    for (int b = threadIdx.x; b < half; b += blockDim.x) {
-      const int p = b >> ls, q = b & (s - 1);
-      const float2v u = x[q + s * p], v = x[q + s * (p + 1)];
-      y[q + s * 2 * p] = float2v{u.x + v.x, u.y + v.y};
-      y[q + s * (2 * p + 1)] = cmul(float2v{u.x - v.x, u.y - v.y}, twiddle(tw, p << ls, half, sign));
+    if (r + gridDim.x < rows) fetch(r + gridDim.x);
+    const int half = K >> 1;
+    int ls = 0, n = K;  // log2 of the stride, points per block
+    for (; n >= 4; n >>= 2, ls += 2) {
+      const int m = n >> 2, s = 1 << ls;
+      for (int b = threadIdx.x; b < (K >> 2); b += blockDim.x) {
+        const int p = b >> ls, q = b & (s - 1);
+        const float2v a0 = x[q + s * p], a1 = x[q + s * (p + m)], a2 = x[q + s * (p + 2 * m)],
+                      a3 = x[q + s * (p + 3 * m)];
+        const float2v t0{a0.x + a2.x, a0.y + a2.y}, t1{a0.x - a2.x, a0.y - a2.y};
+        const float2v t2{a1.x + a3.x, a1.y + a3.y}, d{a1.x - a3.x, a1.y - a3.y};
+        // d i^(sign): times -i (forward) or +i (inverse)
+        const float2v t3 = sign > 0 ? float2v{-d.y, d.x} : float2v{d.y, -d.x};
+        const int e = p << ls;  // exponent p s
+        y[q + s * 4 * p] = float2v{t0.x + t2.x, t0.y + t2.y};
+        y[q + s * (4 * p + 1)] = cmul(float2v{t1.x + t3.x, t1.y + t3.y}, twiddle(tw, e, half, sign));
+        y[q + s * (4 * p + 2)] = cmul(float2v{t0.x - t2.x, t0.y - t2.y}, twiddle(tw, 2 * e, half, sign));
+        y[q + s * (4 * p + 3)] = cmul(float2v{t1.x - t3.x, t1.y - t3.y}, twiddle(tw, 3 * e, half, sign));
+      }
+      __syncthreads();
+      float2v *t = x;
+      x = y;
+      y = t;
     }
-    __syncthreads();
-    x = y;
+    if (n == 2) {
+      const int s = 1 << ls;
+      for (int b = threadIdx.x; b < half; b += blockDim.x) {
+        const int p = b >> ls, q = b & (s - 1);
+        const float2v u = x[q + s * p], v = x[q + s * (p + 1)];
+        y[q + s * 2 * p] = float2v{u.x + v.x, u.y + v.y};
+        y[q + s * (2 * p + 1)] = cmul(float2v{u.x - v.x, u.y - v.y}, twiddle(tw, p << ls, half, sign));
+      }
+      __syncthreads();
+      x = y;
+    }
+    float2v *row = data + r * K;
+    for (int i = threadIdx.x; i < K; i += blockDim.x) row[i] = x[i];
   }
-  for (int i = threadIdx.x; i < K; i += blockDim.x) row[i] = x[i];
 }
 
 // out plane [Cc][R] = transpose of in plane [R][Cc], through 32 x 32 LDS tiles
@@ -425,11 +453,15 @@ int launch_fft_rows(float2v *data, int64_t rows, int K, const float2v *tw, int s
   if (rows <= 0) return FHS_OK;
   if (K < 2 || K > kMaxGrid || (K & (K - 1)) != 0) return fail(FHS_EUNSUPPORTED, "FFT length must be a power of two");
   if (rows > 0x7fffffff) return fail(FHS_EUNSUPPORTED, "too many FFT rows");
-  // (one radix-4 butterfly per thread and pass, up to 1024 threads)
+  // (one radix-4 butterfly per thread and pass, up to 1024 threads; as many
+  // workgroups as fit on the 256 CUs at once by LDS and by waves, each walking
+  // its share of the rows)
   const int threads = K / 4 < 1024 ? (K / 4 < 64 ? 64 : K / 4) : 1024;
   const size_t lds = static_cast<size_t>(2 * K) * sizeof(float2v);
-  hipLaunchKernelGGL(fft_rows_kernel, dim3(static_cast<unsigned>(rows)), dim3(threads), lds,
-                     static_cast<hipStream_t>(stream), data, K, tw, sign);
+  const int per_cu = std::max(1, std::min(static_cast<int>((160 * 1024) / lds), 32 / (threads / 64)));
+  const int64_t nwg = std::min<int64_t>(rows, 256 * static_cast<int64_t>(per_cu));
+  hipLaunchKernelGGL(fft_rows_kernel, dim3(static_cast<unsigned>(nwg)), dim3(threads), lds,
+                     static_cast<hipStream_t>(stream), data, rows, K, tw, sign);
   return check("nufft fft rows");
 }
 
