@@ -30,12 +30,14 @@ __device__ __forceinline__ float2v cmul(float2v a, float2v b) {
 // ---------------------------------------------------------------- Z and Z^T
 __global__ void __launch_bounds__(256) pad_kernel(PadArgs a) {
   const int64_t n = static_cast<int64_t>(a.L) * a.K1 * a.K2;
+  // (K1 and K2 are powers of two: indices by shifts and masks)
+  const int lk1 = __ffs(a.K1) - 1, lk2 = __ffs(a.K2) - 1;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int k2 = static_cast<int>(i % a.K2);
-    const int64_t r = i / a.K2;
-    const int k1 = static_cast<int>(r % a.K1);
-    const int l = static_cast<int>(r / a.K1);
+    const int k2 = static_cast<int>(i & (a.K2 - 1));
+    const int64_t r = i >> lk2;
+    const int k1 = static_cast<int>(r & (a.K1 - 1));
+    const int l = static_cast<int>(r >> lk1);
     const int n1 = (k1 < a.K1 / 2 ? k1 : k1 - a.K1) + a.ny / 2;
     const int n2 = (k2 < a.K2 / 2 ? k2 : k2 - a.K2) + a.nx / 2;
     float v = 0.0f;
