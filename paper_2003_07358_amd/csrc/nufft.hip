@@ -91,6 +91,9 @@ __global__ void __launch_bounds__(1024) fft_rows_kernel(float2v *data, int64_t r
                                                         int sign) {
   extern __shared__ float2v buf[];
   const int nthr = static_cast<int>(blockDim.x);
+  // the twiddle table in LDS after the two row buffers, loaded once per workgroup
+  float2v *twl = buf + 2 * K;
+  for (int i = threadIdx.x; i < (K >> 1); i += nthr) twl[i] = tw[i];
   float2v pre[kFftMaxPer];
   auto fetch = [&](int64_t r) __attribute__((always_inline)) {
     const float2v *src = data + r * K;
@@ -126,9 +129,9 @@ __global__ void __launch_bounds__(1024) fft_rows_kernel(float2v *data, int64_t r
         const float2v t3 = sign > 0 ? float2v{-d.y, d.x} : float2v{d.y, -d.x};
         const int e = p << ls;  // exponent p s
         y[q + s * 4 * p] = float2v{t0.x + t2.x, t0.y + t2.y};
-        y[q + s * (4 * p + 1)] = cmul(float2v{t1.x + t3.x, t1.y + t3.y}, twiddle(tw, e, half, sign));
-        y[q + s * (4 * p + 2)] = cmul(float2v{t0.x - t2.x, t0.y - t2.y}, twiddle(tw, 2 * e, half, sign));
-        y[q + s * (4 * p + 3)] = cmul(float2v{t1.x - t3.x, t1.y - t3.y}, twiddle(tw, 3 * e, half, sign));
+        y[q + s * (4 * p + 1)] = cmul(float2v{t1.x + t3.x, t1.y + t3.y}, twiddle(twl, e, half, sign));
+        y[q + s * (4 * p + 2)] = cmul(float2v{t0.x - t2.x, t0.y - t2.y}, twiddle(twl, 2 * e, half, sign));
+        y[q + s * (4 * p + 3)] = cmul(float2v{t1.x - t3.x, t1.y - t3.y}, twiddle(twl, 3 * e, half, sign));
       }
       __syncthreads();
       float2v *t = x;
@@ -141,7 +144,7 @@ __global__ void __launch_bounds__(1024) fft_rows_kernel(float2v *data, int64_t r
         const int p = b >> ls, q = b & (s - 1);
         const float2v u = x[q + s * p], v = x[q + s * (p + 1)];
         y[q + s * 2 * p] = float2v{u.x + v.x, u.y + v.y};
-        y[q + s * (2 * p + 1)] = cmul(float2v{u.x - v.x, u.y - v.y}, twiddle(tw, p << ls, half, sign));
+        y[q + s * (2 * p + 1)] = cmul(float2v{u.x - v.x, u.y - v.y}, twiddle(twl, p << ls, half, sign));
       }
       __syncthreads();
       x = y;
@@ -459,7 +462,7 @@ int launch_fft_rows(float2v *data, int64_t rows, int K, const float2v *tw, int s
   // workgroups as fit on the 256 CUs at once by LDS and by waves, each walking
   // its share of the rows)
   const int threads = K / 4 < 1024 ? (K / 4 < 64 ? 64 : K / 4) : 1024;
-  const size_t lds = static_cast<size_t>(2 * K) * sizeof(float2v);
+  const size_t lds = static_cast<size_t>(2 * K + K / 2) * sizeof(float2v);  // two row buffers, twiddles
   const int per_cu = std::max(1, std::min(static_cast<int>((160 * 1024) / lds), 32 / (threads / 64)));
   const int64_t nwg = std::min<int64_t>(rows, 256 * static_cast<int64_t>(per_cu));
   hipLaunchKernelGGL(fft_rows_kernel, dim3(static_cast<unsigned>(nwg)), dim3(threads), lds,
